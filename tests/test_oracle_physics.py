@@ -1,0 +1,108 @@
+"""Pins of the whole oracle time step against closed-form flow physics:
+shear-wave decay, the acoustic speed that fixes gamma = (D+n+2)/(D+n)
+(Sec. III), the shock-tube analytical solution (Sec. VI) and the paper's own
+worked example (Sec. VI, Table III)."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import golden
+
+
+def test_shear_wave_viscosity(orc):
+    # Exact streaming with BGK: nu = c_s^2 (tau - 1/2) in node units with
+    # c_s^2 = T / r^2 (xi = r c).  u_y = A sin(k x) decays as exp(-nu k^2 t).
+    L, tau, T0, A = 64, 0.8, 1.0, 0.01
+    G = orc.Grid(orc.D2Q49, (L, 1), n_rot=3.0, tau=tau)
+    x = np.arange(L)
+    u = np.zeros((2, L))
+    u[1] = A * np.sin(2 * np.pi * x / L)
+    f, g = G.init_eq(np.ones(L), u, np.full(L, T0))
+    amps = []
+    for t_target in (50, 300):
+        G.step(f, g, t_target - (50 if amps else 0))
+        uy = G.moments(f, g)[1][1]
+        amps.append(abs(np.fft.rfft(uy)[1]))
+    rate = math.log(amps[0] / amps[1]) / 250.0
+    r = orc.d1q7_r()
+    k = 2 * np.pi / L
+    nu = T0 / r ** 2 * (tau - 0.5)
+    assert rate == pytest.approx(nu * k * k, rel=0.01)
+
+
+@pytest.mark.parametrize("n_rot", [0.0, 2.0, 4.0, 11.0 / 3.0, 19.0])
+def test_acoustic_speed_gives_gamma(orc, n_rot):
+    # A right-moving linear sound wave travels at c = sqrt(gamma T0) in the
+    # paper's units, i.e. c / r nodes per step.
+    L, T0, A, tau = 128, 1.0, 1e-4, 0.6
+    D = 1
+    gamma = (D + n_rot + 2) / (D + n_rot)
+    r = orc.d1q7_r()
+    c = math.sqrt(gamma * T0)
+    x = np.arange(L)
+    s = A * np.cos(2 * np.pi * x / L)
+    G = orc.Grid(orc.D1Q7, (L,), n_rot=n_rot, tau=tau)
+    f, g = G.init_eq(1 + s, (c * s)[None], T0 * (1 + (gamma - 1) * s))
+    phases, times = [], []
+    for t in range(0, 201, 20):
+        if t:
+            G.step(f, g, 20)
+        rho = G.moments(f, g)[0]
+        phases.append(np.angle(np.fft.fft(rho)[1]))
+        times.append(t)
+    ph = np.unwrap(phases)
+    slope = np.polyfit(times, ph, 1)[0]
+    v = -slope / (2 * np.pi / L)  # nodes per step
+    gamma_meas = (v * r) ** 2 / T0
+    assert gamma_meas == pytest.approx(gamma, rel=0.005)
+
+
+def _tube(orc, N, left, right, n_rot, tau, steps, kind=None, ny=None):
+    from oracle import riemann
+    from oracle.metrics import l1_rel_error
+    r = orc.d1q7_r()
+    x = (np.arange(N) + 0.5) / N  # cell-centred, diaphragm at x = 1/2
+    rho = np.where(x < 0.5, left[0], right[0])
+    T = np.where(x < 0.5, left[2] / left[0], right[2] / right[0])
+    if ny:
+        G = orc.Grid(kind, (N, ny), bc=(orc.OPEN, orc.PERIODIC), n_rot=n_rot, tau=tau)
+        f, g = G.init_eq(np.tile(rho, ny), np.zeros((2, N * ny)), np.tile(T, ny))
+    else:
+        G = orc.Grid(orc.D1Q7, (N,), bc=(orc.OPEN,), n_rot=n_rot, tau=tau)
+        f, g = G.init_eq(rho, np.zeros((1, N)), T)
+    G.step(f, g, steps)
+    rr, uu, TT, _ = G.moments(f, g)
+    if ny:
+        row = ny // 2
+        rr, TT, ux = (a.reshape(ny, N)[row] for a in (rr, TT, uu[0]))
+        for a in (G.moments(f, g)[0].reshape(ny, N),):
+            assert np.allclose(a, a[row], rtol=1e-12)  # uniform across the periodic axis
+    else:
+        ux = uu[0]
+    Dm = 2 if ny else 1
+    gamma = (Dm + n_rot + 2) / (Dm + n_rot)
+    t = steps / (N * r)  # Sec. VI: t = step / (X r)
+    ra, ua, pa = riemann.sample(left, right, gamma, (x - 0.5) / t)
+    return {"rho": l1_rel_error(rr, ra), "p": l1_rel_error(rr * TT, pa),
+            "T": l1_rel_error(TT, pa / ra), "u_x": l1_rel_error(ux, ua)}
+
+
+@pytest.mark.parametrize("steps", [180, 239])
+def test_shock_tube_1d_vs_exact_riemann(orc, steps):
+    # The paper's tube (rho 4:1, T = 1) in 1-D with n = 4 (gamma = 1.4).
+    e = _tube(orc, 1000, (4.0, 0.0, 4.0), (1.0, 0.0, 1.0), 4.0, 2.0 / 3.0, steps)
+    assert e["rho"] < 2e-2 and e["p"] < 2e-2 and e["T"] < 2e-2 and e["u_x"] < 4e-2, e
+
+
+@pytest.mark.slow
+def test_paper_worked_example_table3(orc):
+    # Sec. VI exactly: D2Q37 + D1Q7 on 1000 x 16, open in x, periodic in y,
+    # n = 3, tau = 2/3, step 180.  The paper's errors (Table III) come from a
+    # code we do not have; agreement within a factor 2 either way confirms
+    # the collide-and-stream reading of the translational update.
+    e = _tube(orc, 1000, (4.0, 0.0, 4.0), (1.0, 0.0, 1.0), 3.0, 2.0 / 3.0, 180,
+              kind=orc.D2Q37, ny=16)
+    table = {k: float(v) for k, v in golden("table3_errors.txt")}
+    for k, v in table.items():
+        assert v / 2.0 <= e[k] <= 2.0 * v, (k, e[k], v)
