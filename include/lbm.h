@@ -1,0 +1,202 @@
+/*
+ * lbm.h -- C ABI of liblbmx, an MI355X (gfx950) implementation of the
+ * decoupled Hermite-expansion lattice Boltzmann scheme for compressible flow
+ * with arbitrary specific heat ratio (Hu, Zhang & Geng, arXiv:1606.06107).
+ *
+ * The scheme (Secs. II-V of the paper) advances two population sets per node:
+ *   f_i  translational populations (the paper's g_i) on a Gauss-Hermite
+ *        lattice: D1Q7, or its tensor powers D2Q49, D3Q343 (Table II, Sec. IV).
+ *        Streamed with xi_i = r c_i: collide, then shift by the integer c_i.
+ *   g_j  rotational populations (the paper's h_j) on D1Q7, eta_j = r j:
+ *        advected with the fluid velocity u by the third-order upwind
+ *        difference of Sec. V A with forward-Euler time stepping, and relaxed.
+ * Both relax with BGK (omega = 1/tau, tau in time steps) towards the
+ * fourth-order Hermite equilibria of Sec. IV evaluated at the node's
+ * (rho, u, T).  T comes from the total energy with D+n degrees of freedom
+ * (Sec. V B step 4), so gamma = (D+n+2)/(D+n) (Sec. III).
+ * Units are the paper's dimensionless ones (T0 = R_g = 1).  A step moves a
+ * population c_i nodes, i.e. dt = dx / r; the rotational Courant number along
+ * axis a is u_a / r.
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns lbm_status (LBM_OK = 0) and never throws or aborts.
+ *    On failure lbm_last_error() returns a message (thread-local).
+ *  - Every pointer argument named f, g, rho, u, T, totals, offsets, ... is a
+ *    DEVICE pointer, allocated and owned by the caller (e.g. a torch tensor);
+ *    it must stay valid while any handle or launch uses it.  The library owns
+ *    only host-side handles and the HIP graphs it instantiates.
+ *  - Work is enqueued asynchronously on the caller's HIP stream (hipStream_t
+ *    passed as void*; NULL = the null stream).  The host sees argument and
+ *    launch errors only; numerical failure (non-finite values, rho <= 0,
+ *    T <= 0) is reported in device memory (totals, status) that the caller
+ *    reads after synchronising the stream.
+ *  - Population arrays are structure-of-arrays [Q][N], node index x fastest:
+ *    node(x,y,z) = x + nx*(y + ny*z).  Lattice direction i of D1Q7^D is
+ *    i = cx+3 (1-D), (cy+3)*7 + cx+3 (2-D), ((cz+3)*7 + cy+3)*7 + cx+3 (3-D).
+ *  - Macroscopic fields are FP64: rho[N], u[D][N], T[N].
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+typedef int32_t lbm_status;
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,       /* invalid argument or descriptor */
+    LBM_EDEVICE = 2,      /* no usable gfx950 device, or a HIP runtime error */
+    LBM_ENOMEM = 3,       /* host allocation failed */
+    LBM_EUNSUPPORTED = 4, /* valid but not implemented combination */
+    LBM_ELAUNCH = 5       /* kernel launch or graph error */
+};
+
+/* Translational lattices (Table II and its tensor powers). */
+enum { LBM_D1Q7 = 1, LBM_D2Q49 = 2, LBM_D3Q343 = 3 };
+/* Population storage type. */
+enum { LBM_F32 = 0, LBM_F64 = 1 };
+/* Boundary condition per axis: periodic wrap, or open (zero-gradient clamp
+ * of the streaming source index and of the upwind stencil; Sec. VI uses open
+ * left/right ends). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_OPEN = 1 };
+
+typedef struct {
+    int32_t abi_version; /* must equal LBM_ABI_VERSION */
+    int32_t dim;         /* spatial dimension D: 1, 2 or 3 (must match lattice) */
+    int64_t n[3];        /* nodes per axis; unused axes must be 1.  Periodic axes
+                            need n >= 3; N = n0*n1*n2 < 2^31 */
+    int32_t lattice;     /* LBM_D1Q7, LBM_D2Q49 or LBM_D3Q343 */
+    int32_t dtype;       /* LBM_F32 or LBM_F64 population storage */
+    int32_t bc[3];       /* LBM_BC_PERIODIC or LBM_BC_OPEN per axis */
+    double n_rot;        /* rotational degrees of freedom n >= 0 (real);
+                            gamma = (D+n+2)/(D+n) */
+    double tau;          /* BGK relaxation time in time steps, tau > 0.5 */
+    void *f[2];          /* two device buffers [Q][N] of dtype (ping-pong) */
+    void *g[2];          /* two device buffers [7][N] of dtype (ping-pong) */
+    void *workspace;     /* device scratch of lbm_workspace_bytes() bytes, 256-B
+                            aligned (reduction partials); caller-owned */
+} lbm_desc;
+
+typedef struct lbm_sim_s *lbm_sim; /* opaque host handle; owns no device memory */
+
+/* Bytes of device workspace a descriptor needs (0 on an invalid descriptor). */
+size_t lbm_workspace_bytes(const lbm_desc *desc);
+
+/* Validate desc, create a handle bound to hip_stream and set every node to
+ * equilibrium: f = f^eq(rho, u, T), g = g^eq(T) (Sec. IV), written to f[0],
+ * g[0].  rho[N], u[D][N], T[N]: device FP64 fields.  Time is 0 afterwards.
+ * Errors: LBM_EINVAL (descriptor, NULL pointers), LBM_EDEVICE, LBM_ELAUNCH. */
+lbm_status lbm_init(const lbm_desc *desc, const double *rho, const double *u,
+                    const double *T, void *hip_stream, lbm_sim *out);
+
+/* As lbm_init, but the state at time 0 is given as populations: f0[Q][N] and
+ * g0[7][N] of the descriptor's dtype, copied into f[0], g[0] (device). */
+lbm_status lbm_init_populations(const lbm_desc *desc, const void *f0, const void *g0,
+                                void *hip_stream, lbm_sim *out);
+
+/* Advance nsteps >= 0 time steps (Sec. V B steps 1-5, one fused kernel per
+ * step: gather of the streamed f, FP64 moments and temperature, Hermite
+ * equilibria, BGK, upwind advection of g, boundary conditions).  With graphs
+ * enabled (default) and nsteps > 1 the steps replay as one HIP graph.
+ * Errors: LBM_EINVAL, LBM_ELAUNCH. */
+lbm_status lbm_step(lbm_sim sim, int64_t nsteps);
+
+/* Fields and conservation totals at the current time.  rho[N], u[D][N], T[N]
+ * and totals[2+D] = {mass, momentum_0..D-1, energy} (energy = sum over nodes
+ * of E_t + rho e_r, i.e. rho (|u|^2/2 + (D+n)T/2)), all device FP64; any may
+ * be NULL to skip.  Moments are accumulated in FP64 from the populations and
+ * T is extracted in FP64 (Sec. V B steps 3-4); totals use a deterministic
+ * fixed-order two-stage reduction. */
+lbm_status lbm_moments(lbm_sim sim, double *rho, double *u, double *T, double *totals);
+
+/* Populations at the current time in canonical form (streamed translational
+ * populations f(t), rotational g(t)), written to device buffers f_out[Q][N],
+ * g_out[7][N] of the descriptor's dtype; either may be NULL. */
+lbm_status lbm_populations(lbm_sim sim, void *f_out, void *g_out);
+
+/* Record conservation totals every `every` steps during lbm_step, fused into
+ * the step kernel: row k of series[capacity][2+D] (device FP64) receives the
+ * totals of time t with t = k*every (t counted from lbm_init).  Steps whose
+ * row is >= capacity record nothing.  every = 0 switches recording off. */
+lbm_status lbm_set_monitor(lbm_sim sim, int64_t every, double *series, int64_t capacity);
+
+/* Time-step counter since lbm_init. */
+lbm_status lbm_time(lbm_sim sim, int64_t *t);
+
+/* Enable (1) or disable (0) HIP-graph replay of multi-step calls. */
+lbm_status lbm_set_graphs(lbm_sim sim, int32_t enable);
+
+/* Launch shape of the step kernel: nodes per workgroup tile along x, y, z
+ * (product 64..1024, a multiple of 64; tile_x a multiple of 16).  Used by the
+ * autotuner; results do not depend on it.  LBM_EUNSUPPORTED if the shape is
+ * not compiled. */
+lbm_status lbm_set_tile(lbm_sim sim, int32_t tx, int32_t ty, int32_t tz);
+
+/* Release the handle and its graphs (NULL-safe).  Device buffers are the
+ * caller's. */
+lbm_status lbm_destroy(lbm_sim sim);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Lattice constants the library computes with: Q, r, and (if not NULL) the
+ * weights w[Q] and velocities c[Q][3] (integers).  Host pointers. */
+lbm_status lbm_lattice_info(int32_t lattice, int32_t *Q, double *r, double *w, int32_t *c);
+
+/* ------------------------------------------------------------------------ */
+/* Batched 1-D shock tubes: one persistent launch advances many independent  */
+/* D1Q7 + D1Q7 tubes of uneven length, each with its own n, tau and number   */
+/* of steps, both ends open (Sec. VI boundary treatment).                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t abi_version;    /* LBM_ABI_VERSION */
+    int32_t dtype;          /* LBM_F32 or LBM_F64 */
+    int64_t num_instances;  /* I >= 1 */
+    int64_t total_nodes;    /* sum of lengths = offsets[I] < 2^31 */
+    const int64_t *offsets; /* device [I+1], offsets[0] = 0, increasing; tube i
+                               owns packed nodes offsets[i] .. offsets[i+1]-1,
+                               length >= 4 */
+    const double *n_rot;    /* device [I], n >= 0 */
+    const double *tau;      /* device [I], tau > 0.5 */
+    const int64_t *nsteps;  /* device [I], steps to advance in lbm_batch_step, >= 0 */
+    void *f[2];             /* device [7][total] of dtype: f[0] holds the state,
+                               f[1] is scratch */
+    void *g[2];             /* device [7][total] of dtype: same roles */
+    int32_t *status;        /* device [I] out: 0 ok, 1 non-finite, 2 rho<=0 or T<=0 */
+    void *workspace;        /* device, lbm_batch_workspace_bytes() bytes */
+    int32_t block;          /* threads per workgroup: 256, 512 or 1024 (0 = default) */
+    int32_t chunk;          /* nodes per on-chip chunk, 0 = largest that fits */
+    int32_t superstep;      /* time steps per on-chip pass of a chunked tube
+                               (0 = default 32) */
+} lbm_batch_desc;
+
+size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc);
+
+/* Equilibrium initial state of every tube from packed FP64 fields rho[total],
+ * u[total], T[total] (device). */
+lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const double *u,
+                          const double *T, void *hip_stream);
+
+/* Advance every tube i by nsteps[i] steps in ONE persistent launch: each
+ * workgroup takes tubes longest-work-first from a device queue and runs the
+ * whole time loop of a tube on chip (tubes longer than one chunk advance in
+ * passes of `superstep` steps with overlapping halos).  The result is left in
+ * f[0], g[0]; status[i] is written at the end. */
+lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream);
+
+/* Packed FP64 fields rho[total], u[total], T[total] of the state in f[0], g[0];
+ * any may be NULL. */
+lbm_status lbm_batch_moments(const lbm_batch_desc *desc, double *rho, double *u, double *T,
+                             void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,427 @@
+// C-ABI host library (declarations and contracts in include/lbm.h):
+// argument validation, kernel launches on the caller's stream, HIP-graph
+// capture and replay of multi-step calls, error strings.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "lbm.h"
+#include "lbm_device.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+lbm_status hip_fail(hipError_t e, const char *what) {
+    return fail(LBM_ELAUNCH, "%s: %s", what, hipGetErrorString(e));
+}
+
+// The library targets gfx950 (MI355X) only.
+lbm_status check_device() {
+    int dev = 0, count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(LBM_EDEVICE, "no HIP device available");
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LBM_EDEVICE, "hipGetDevice failed");
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return fail(LBM_EDEVICE, "hipGetDeviceProperties failed");
+    if (strncmp(p.gcnArchName, "gfx950", 6) != 0)
+        return fail(LBM_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
+                    p.gcnArchName);
+    return LBM_OK;
+}
+
+int q_of(int lattice) { return lattice == LBM_D1Q7 ? 7 : lattice == LBM_D2Q49 ? 49 : 343; }
+size_t pop_bytes(int dtype) { return dtype == LBM_F32 ? 4 : 8; }
+
+void default_tile(int dim, int tile[3]) {
+    tile[2] = 1;
+    if (dim == 1) { tile[0] = 256; tile[1] = 1; }
+    else if (dim == 2) { tile[0] = 64; tile[1] = 4; }
+    else { tile[0] = 64; tile[1] = 1; }
+}
+
+// Largest number of per-tile partial rows any supported launch can produce.
+int64_t max_partial_rows(const lbm_desc *d) {
+    const int64_t N = d->n[0] * d->n[1] * d->n[2];
+    int64_t rows = (N + 255) / 256;  // field kernel
+    static const int cand[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {1024, 1}, {64, 4},
+                                  {32, 8}, {128, 2}, {64, 8}, {32, 16}, {16, 16}, {64, 2},
+                                  {32, 2}, {16, 4}};
+    for (auto &c : cand) {
+        const int t[3] = {c[0], c[1], 1};
+        int a, b, e;
+        if (d->dim == 1 && c[1] != 1) continue;
+        const int64_t n = lbmx::step_ntiles(d->dim, t, (int)d->n[0], (int)d->n[1], (int)d->n[2],
+                                            &a, &b, &e);
+        if (n > rows) rows = n;
+    }
+    return rows;
+}
+
+lbm_status validate(const lbm_desc *d) {
+    if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
+    if (d->abi_version != LBM_ABI_VERSION)
+        return fail(LBM_EINVAL, "abi_version %d != %d", d->abi_version, LBM_ABI_VERSION);
+    if (d->dim < 1 || d->dim > 3) return fail(LBM_EINVAL, "dim must be 1, 2 or 3");
+    const int want = d->dim == 1 ? LBM_D1Q7 : d->dim == 2 ? LBM_D2Q49 : LBM_D3Q343;
+    if (d->lattice != want)
+        return fail(LBM_EINVAL, "lattice %d does not match dim %d", d->lattice, d->dim);
+    if (d->dtype != LBM_F32 && d->dtype != LBM_F64) return fail(LBM_EINVAL, "dtype must be F32 or F64");
+    int64_t N = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (d->n[a] < 1) return fail(LBM_EINVAL, "n[%d] = %lld < 1", a, (long long)d->n[a]);
+        if (a >= d->dim && d->n[a] != 1) return fail(LBM_EINVAL, "unused axis %d must have n = 1", a);
+        if (a < d->dim && d->bc[a] != LBM_BC_PERIODIC && d->bc[a] != LBM_BC_OPEN)
+            return fail(LBM_EINVAL, "bc[%d] invalid", a);
+        if (a < d->dim && d->bc[a] == LBM_BC_PERIODIC && d->n[a] < 3)
+            return fail(LBM_EINVAL, "periodic axis %d needs n >= 3", a);
+        if (d->n[a] > (1LL << 30)) return fail(LBM_EINVAL, "n[%d] too large", a);
+        N *= d->n[a];
+        if (N >= (1LL << 31)) return fail(LBM_EINVAL, "N must be < 2^31");
+    }
+    if (!(d->n_rot >= 0.0) || !isfinite(d->n_rot)) return fail(LBM_EINVAL, "n_rot must be >= 0");
+    if (!(d->tau > 0.5) || !isfinite(d->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
+    if (!d->f[0] || !d->f[1] || !d->g[0] || !d->g[1])
+        return fail(LBM_EINVAL, "population buffers must not be NULL");
+    if (d->f[0] == d->f[1] || d->g[0] == d->g[1] || d->f[0] == d->g[0] || d->f[1] == d->g[1])
+        return fail(LBM_EINVAL, "population buffers must be distinct");
+    if (!d->workspace) return fail(LBM_EINVAL, "workspace must not be NULL");
+    if (((uintptr_t)d->workspace) % 256) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_sim_s {
+    lbm_desc d;
+    hipStream_t stream;    // caller's stream
+    hipStream_t capture;   // private stream used only to record graphs
+    int cur = 0;           // buffer index of the current state
+    int streamed = 1;      // f[cur] holds streamed populations (just initialised)
+    int64_t t = 0;
+    int tile[3];
+    int graphs = 1;
+    int64_t mon_every = 0;
+    double *mon_series = nullptr;
+    int64_t mon_cap = 0;
+    struct Entry {
+        int64_t n, t0, every;
+        int cur, streamed, tile0, tile1;
+        double *series;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> cache;
+};
+
+namespace {
+
+void clear_cache(lbm_sim s) {
+    for (auto &e : s->cache) hipGraphExecDestroy(e.exec);
+    s->cache.clear();
+}
+
+int64_t N_of(const lbm_desc &d) { return d.n[0] * d.n[1] * d.n[2]; }
+
+// Enqueue one time step on stream st and advance the host-side state.
+hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
+    const lbm_desc &d = s->d;
+    lbmx::StepArgs a;
+    a.f_in = d.f[s->cur];
+    a.g_in = d.g[s->cur];
+    a.f_out = d.f[s->cur ^ 1];
+    a.g_out = d.g[s->cur ^ 1];
+    a.n0 = (int)d.n[0];
+    a.n1 = (int)d.n[1];
+    a.n2 = (int)d.n[2];
+    a.open0 = d.dim >= 1 && d.bc[0] == LBM_BC_OPEN;
+    a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
+    a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
+    a.N = (uint32_t)N_of(d);
+    a.streamed = s->streamed;
+    a.omega = 1.0 / d.tau;
+    a.n_rot = d.n_rot;
+    a.ntiles = lbmx::step_ntiles(d.dim, s->tile, a.n0, a.n1, a.n2, &a.tiles0, &a.tiles1, &a.tiles2);
+    const bool mon = s->mon_every > 0 && s->t % s->mon_every == 0 &&
+                     s->t / s->mon_every < s->mon_cap;
+    a.partials = mon ? (double *)d.workspace : nullptr;
+    hipError_t e = lbmx::launch_step(d.dtype, d.dim, s->tile, a, st);
+    if (e != hipSuccess) return e;
+    if (mon) {
+        const int K = 2 + d.dim;
+        e = lbmx::launch_reduce((const double *)d.workspace, a.ntiles, K,
+                                s->mon_series + (s->t / s->mon_every) * K, st);
+        if (e != hipSuccess) return e;
+    }
+    s->cur ^= 1;
+    s->streamed = 0;
+    s->t += 1;
+    return hipSuccess;
+}
+
+lbm_status make_sim(const lbm_desc *desc, void *stream, lbm_sim *out) {
+    lbm_status st = validate(desc);
+    if (st) return st;
+    if (!out) return fail(LBM_EINVAL, "out handle pointer is NULL");
+    st = check_device();
+    if (st) return st;
+    lbm_sim s = new (std::nothrow) lbm_sim_s();
+    if (!s) return fail(LBM_ENOMEM, "out of host memory");
+    s->d = *desc;
+    s->stream = (hipStream_t)stream;
+    default_tile(desc->dim, s->tile);
+    if (hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return fail(LBM_EDEVICE, "hipStreamCreateWithFlags failed");
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_desc *desc) {
+    if (!desc || desc->dim < 1 || desc->dim > 3) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (desc->n[a] < 1) return 0;
+    const size_t rows = (size_t)max_partial_rows(desc);
+    return ((rows * (2 + desc->dim) * sizeof(double) + 255) / 256) * 256;
+}
+
+lbm_status lbm_init(const lbm_desc *desc, const double *rho, const double *u, const double *T,
+                    void *hip_stream, lbm_sim *out) {
+    if (!rho || !u || !T) return fail(LBM_EINVAL, "rho, u and T must not be NULL");
+    lbm_sim s = nullptr;
+    lbm_status st = make_sim(desc, hip_stream, &s);
+    if (st) return st;
+    lbmx::InitArgs a{rho, u, T, desc->f[0], desc->g[0], (uint32_t)N_of(*desc)};
+    hipError_t e = lbmx::launch_init(desc->dtype, desc->dim, a, s->stream);
+    if (e != hipSuccess) {
+        lbm_destroy(s);
+        return hip_fail(e, "init launch");
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_populations(const lbm_desc *desc, const void *f0, const void *g0,
+                                void *hip_stream, lbm_sim *out) {
+    if (!f0 || !g0) return fail(LBM_EINVAL, "f0 and g0 must not be NULL");
+    lbm_sim s = nullptr;
+    lbm_status st = make_sim(desc, hip_stream, &s);
+    if (st) return st;
+    const size_t N = (size_t)N_of(*desc), b = pop_bytes(desc->dtype);
+    hipError_t e = hipSuccess;
+    if (f0 != desc->f[0])
+        e = hipMemcpyAsync(desc->f[0], f0, (size_t)q_of(desc->lattice) * N * b,
+                           hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && g0 != desc->g[0])
+        e = hipMemcpyAsync(desc->g[0], g0, 7 * N * b, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) {
+        lbm_destroy(s);
+        return hip_fail(e, "population copy");
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_sim s, int64_t nsteps) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return LBM_OK;
+    if (!s->graphs || nsteps == 1) {
+        for (int64_t k = 0; k < nsteps; ++k) {
+            hipError_t e = enqueue_step(s, s->stream);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+        }
+        return LBM_OK;
+    }
+    const bool mon = s->mon_every > 0;
+    const int64_t t0key = mon ? s->t : -1;
+    for (auto &en : s->cache) {
+        if (en.n == nsteps && en.cur == s->cur && en.streamed == s->streamed && en.t0 == t0key &&
+            en.tile0 == s->tile[0] && en.tile1 == s->tile[1] && en.every == s->mon_every &&
+            en.series == s->mon_series) {
+            hipError_t e = hipGraphLaunch(en.exec, s->stream);
+            if (e != hipSuccess) return hip_fail(e, "graph launch");
+            s->cur = (int)((s->cur + nsteps) & 1);
+            s->streamed = 0;
+            s->t += nsteps;
+            return LBM_OK;
+        }
+    }
+    // Record nsteps launches on the private stream and replay them as one graph.
+    const int cur0 = s->cur, str0 = s->streamed;
+    const int64_t t0 = s->t;
+    hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue_step(s, s->capture);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->capture, &graph);
+    s->cur = cur0;
+    s->streamed = str0;
+    s->t = t0;
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    if (s->cache.size() >= 8) {
+        hipGraphExecDestroy(s->cache.front().exec);
+        s->cache.erase(s->cache.begin());
+    }
+    s->cache.push_back({nsteps, t0key, s->mon_every, cur0, str0, s->tile[0], s->tile[1],
+                        s->mon_series, exec});
+    e = hipGraphLaunch(exec, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    s->cur = (int)((cur0 + nsteps) & 1);
+    s->streamed = 0;
+    s->t = t0 + nsteps;
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_sim s, double *rho, double *u, double *T, double *totals) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    const lbm_desc &d = s->d;
+    lbmx::FieldArgs a = {};
+    a.f = d.f[s->cur];
+    a.g = d.g[s->cur];
+    a.n0 = (int)d.n[0];
+    a.n1 = (int)d.n[1];
+    a.n2 = (int)d.n[2];
+    a.open0 = d.bc[0] == LBM_BC_OPEN;
+    a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
+    a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
+    a.N = (uint32_t)N_of(d);
+    a.streamed = s->streamed;
+    a.n_rot = d.n_rot;
+    a.rho = rho;
+    a.u = u;
+    a.T = T;
+    a.partials = totals ? (double *)d.workspace : nullptr;
+    if (!rho && !u && !T && !totals) return LBM_OK;
+    int nb = 0;
+    hipError_t e = lbmx::launch_fields(d.dtype, d.dim, a, &nb, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "moments launch");
+    if (totals) {
+        e = lbmx::launch_reduce((const double *)d.workspace, nb, 2 + d.dim, totals, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_populations(lbm_sim s, void *f_out, void *g_out) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (!f_out && !g_out) return LBM_OK;
+    const lbm_desc &d = s->d;
+    for (int k = 0; k < 2; ++k)
+        if ((f_out && (f_out == d.f[k] || f_out == d.g[k])) ||
+            (g_out && (g_out == d.f[k] || g_out == d.g[k])))
+            return fail(LBM_EINVAL, "export buffers must differ from the state buffers");
+    lbmx::FieldArgs a = {};
+    a.f = d.f[s->cur];
+    a.g = d.g[s->cur];
+    a.n0 = (int)d.n[0];
+    a.n1 = (int)d.n[1];
+    a.n2 = (int)d.n[2];
+    a.open0 = d.bc[0] == LBM_BC_OPEN;
+    a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
+    a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
+    a.N = (uint32_t)N_of(d);
+    a.streamed = s->streamed;
+    a.f_out = f_out;
+    a.g_out = g_out;
+    hipError_t e = lbmx::launch_export(d.dtype, d.dim, a, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "export launch");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_monitor(lbm_sim s, int64_t every, double *series, int64_t capacity) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (every < 0 || capacity < 0) return fail(LBM_EINVAL, "every and capacity must be >= 0");
+    if (every > 0 && (!series || capacity == 0))
+        return fail(LBM_EINVAL, "series buffer and capacity required when every > 0");
+    s->mon_every = every;
+    s->mon_series = every > 0 ? series : nullptr;
+    s->mon_cap = every > 0 ? capacity : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_time(lbm_sim s, int64_t *t) {
+    if (!s || !t) return fail(LBM_EINVAL, "NULL argument");
+    *t = s->t;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graphs(lbm_sim s, int32_t enable) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    s->graphs = enable ? 1 : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_sim s, int32_t tx, int32_t ty, int32_t tz) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    const int t[3] = {tx, ty, tz};
+    if (!lbmx::step_tile_supported(s->d.dtype, s->d.dim, t))
+        return fail(LBM_EUNSUPPORTED, "tile %dx%dx%d not compiled for dim %d", tx, ty, tz, s->d.dim);
+    s->tile[0] = tx;
+    s->tile[1] = ty;
+    s->tile[2] = tz;
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_sim s) {
+    if (!s) return LBM_OK;
+    clear_cache(s);
+    if (s->capture) hipStreamDestroy(s->capture);
+    delete s;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_lattice_info(int32_t lattice, int32_t *Q, double *r, double *w, int32_t *c) {
+    if (lattice != LBM_D1Q7 && lattice != LBM_D2Q49 && lattice != LBM_D3Q343)
+        return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+    const int q = q_of(lattice);
+    const int D = lattice == LBM_D1Q7 ? 1 : lattice == LBM_D2Q49 ? 2 : 3;
+    if (Q) *Q = q;
+    if (r) *r = lbmx::kR;
+    for (int i = 0; i < q; ++i) {
+        const int cx = lbmx::cx_of(i), cy = D >= 2 ? lbmx::cy_of(i) : 0, cz = D >= 3 ? lbmx::cz_of(i) : 0;
+        if (w)
+            w[i] = lbmx::kW1[cx < 0 ? -cx : cx] * (D >= 2 ? lbmx::kW1[cy < 0 ? -cy : cy] : 1.0) *
+                   (D >= 3 ? lbmx::kW1[cz < 0 ? -cz : cz] : 1.0);
+        if (c) {
+            c[3 * i] = cx;
+            c[3 * i + 1] = cy;
+            c[3 * i + 2] = cz;
+        }
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+"""Python front end of the per-step simulator (lbm_init / lbm_step /
+lbm_moments / lbm_populations).  PyTorch provides device memory and the
+stream; the library's kernels do the work."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_LATTICE = {1: L.LBM_D1Q7, 2: L.LBM_D2Q49, 3: L.LBM_D3Q343}
+_Q = {1: 7, 2: 49, 3: 343}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def lattice_info(dim: int):
+    """(Q, r, w[Q], c[Q,3]) as the library computes with them."""
+    import numpy as np
+    lib = L.load()
+    Q = ctypes.c_int32()
+    r = ctypes.c_double()
+    q = _Q[dim]
+    w = np.zeros(q)
+    c = np.zeros((q, 3), dtype=np.int32)
+    L.check(lib.lbm_lattice_info(_LATTICE[dim], ctypes.byref(Q), ctypes.byref(r),
+                                 w.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p)))
+    return Q.value, r.value, w, c
+
+
+class Sim:
+    """A grid of nodes on one GPU.
+
+    shape: nodes per axis (x first), bc: 'periodic' | 'open' per axis,
+    n_rot: rotational degrees of freedom (gamma = (D+n+2)/(D+n)), tau: BGK
+    relaxation time in steps, dtype: torch.float32 | torch.float64."""
+
+    def __init__(self, shape, bc=None, n_rot=0.0, tau=1.0, dtype=torch.float32,
+                 device="cuda", stream=None):
+        self.lib = L.load()
+        shape = tuple(int(s) for s in shape)
+        self.D = len(shape)
+        assert 1 <= self.D <= 3
+        self.shape = shape
+        self.N = 1
+        for s in shape:
+            self.N *= s
+        self.Q = _Q[self.D]
+        bc = bc or ["periodic"] * self.D
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.f = [torch.empty((self.Q, self.N), dtype=dtype, device=self.device) for _ in range(2)]
+        self.g = [torch.empty((7, self.N), dtype=dtype, device=self.device) for _ in range(2)]
+        d = L.LbmDesc()
+        d.abi_version = L.LBM_ABI_VERSION
+        d.dim = self.D
+        n = list(shape) + [1] * (3 - self.D)
+        for a in range(3):
+            d.n[a] = n[a]
+            d.bc[a] = L.LBM_BC_OPEN if (a < self.D and bc[a] == "open") else L.LBM_BC_PERIODIC
+        d.lattice = _LATTICE[self.D]
+        d.dtype = L.LBM_F32 if dtype == torch.float32 else L.LBM_F64
+        d.n_rot = float(n_rot)
+        d.tau = float(tau)
+        for k in range(2):
+            d.f[k] = self.f[k].data_ptr()
+            d.g[k] = self.g[k].data_ptr()
+        nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(d))
+        self.workspace = torch.empty(max(nbytes, 256) // 8, dtype=torch.float64, device=self.device)
+        d.workspace = self.workspace.data_ptr()
+        self.desc = d
+        self.handle = None
+        self.n_rot, self.tau = float(n_rot), float(tau)
+
+    def _stream_ptr(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def init(self, rho, u, T):
+        """Equilibrium initial state from FP64 fields rho[N], u[D,N], T[N]
+        (numpy or torch; copied to the device)."""
+        dev = self.device
+        self._fields = [torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+                        for a in (rho, u, T)]
+        rho_t, u_t, T_t = self._fields
+        assert rho_t.numel() == self.N and u_t.numel() == self.D * self.N and T_t.numel() == self.N
+        self._free()
+        h = ctypes.c_void_p()
+        with torch.cuda.stream(self.stream):
+            L.check(self.lib.lbm_init(ctypes.byref(self.desc), _ptr(rho_t), _ptr(u_t), _ptr(T_t),
+                                      self._stream_ptr(), ctypes.byref(h)))
+        self.handle = h
+        return self
+
+    def init_populations(self, f0, g0):
+        f0 = torch.as_tensor(f0).to(self.device, self.dtype).contiguous()
+        g0 = torch.as_tensor(g0).to(self.device, self.dtype).contiguous()
+        assert f0.shape == (self.Q, self.N) and g0.shape == (7, self.N)
+        self._keep = (f0, g0)
+        self._free()
+        h = ctypes.c_void_p()
+        L.check(self.lib.lbm_init_populations(ctypes.byref(self.desc), _ptr(f0), _ptr(g0),
+                                              self._stream_ptr(), ctypes.byref(h)))
+        self.handle = h
+        return self
+
+    def step(self, nsteps=1):
+        L.check(self.lib.lbm_step(self.handle, int(nsteps)))
+        return self
+
+    def set_graphs(self, on: bool):
+        L.check(self.lib.lbm_set_graphs(self.handle, 1 if on else 0))
+
+    def set_tile(self, tx, ty=1, tz=1):
+        L.check(self.lib.lbm_set_tile(self.handle, int(tx), int(ty), int(tz)))
+
+    def set_monitor(self, every, capacity):
+        """Record totals every `every` steps into a device tensor [capacity, 2+D]."""
+        self.series = torch.full((int(capacity), 2 + self.D), float("nan"), dtype=torch.float64,
+                                 device=self.device)
+        L.check(self.lib.lbm_set_monitor(self.handle, int(every), _ptr(self.series), int(capacity)))
+        return self.series
+
+    @property
+    def t(self):
+        v = ctypes.c_int64()
+        L.check(self.lib.lbm_time(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def moments(self, fields=True, totals=True):
+        """(rho[N], u[D,N], T[N], totals[2+D]) as FP64 device tensors."""
+        dev = self.device
+        rho = torch.empty(self.N, dtype=torch.float64, device=dev) if fields else None
+        u = torch.empty((self.D, self.N), dtype=torch.float64, device=dev) if fields else None
+        T = torch.empty(self.N, dtype=torch.float64, device=dev) if fields else None
+        tot = torch.empty(2 + self.D, dtype=torch.float64, device=dev) if totals else None
+        L.check(self.lib.lbm_moments(self.handle, _ptr(rho), _ptr(u), _ptr(T), _ptr(tot)))
+        return rho, u, T, tot
+
+    def populations(self):
+        """Streamed f(t) [Q,N] and g(t) [7,N] as device tensors."""
+        f = torch.empty((self.Q, self.N), dtype=self.dtype, device=self.device)
+        g = torch.empty((7, self.N), dtype=self.dtype, device=self.device)
+        L.check(self.lib.lbm_populations(self.handle, _ptr(f), _ptr(g)))
+        return f, g
+
+    def _free(self):
+        if self.handle is not None:
+            self.lib.lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self._free()
+        except Exception:
+            pass
