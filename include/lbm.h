@@ -70,7 +70,7 @@ typedef struct {
     int32_t abi_version; /* must equal LBM_ABI_VERSION */
     int32_t dim;         /* spatial dimension D: 1, 2 or 3 (must match lattice) */
     int64_t n[3];        /* nodes per axis; unused axes must be 1.  Periodic axes
-                            need n >= 3; N = n0*n1*n2 < 2^31 */
+                            need n >= 3; N = n0*n1*n2 with N * sizeof(pop) < 2^32 */
     int32_t lattice;     /* LBM_D1Q7, LBM_D2Q49 or LBM_D3Q343 */
     int32_t dtype;       /* LBM_F32 or LBM_F64 population storage */
     int32_t bc[3];       /* LBM_BC_PERIODIC or LBM_BC_OPEN per axis */

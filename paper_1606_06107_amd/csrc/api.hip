@@ -98,6 +98,8 @@ lbm_status validate(const lbm_desc *d) {
         N *= d->n[a];
         if (N >= (1LL << 31)) return fail(LBM_EINVAL, "N must be < 2^31");
     }
+    if ((uint64_t)N * (d->dtype == LBM_F32 ? 4u : 8u) >= (1ULL << 32))
+        return fail(LBM_EINVAL, "N * sizeof(population) must be < 2^32 bytes per population");
     if (!(d->n_rot >= 0.0) || !isfinite(d->n_rot)) return fail(LBM_EINVAL, "n_rot must be >= 0");
     if (!(d->tau > 0.5) || !isfinite(d->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
     if (!d->f[0] || !d->f[1] || !d->g[0] || !d->g[1])

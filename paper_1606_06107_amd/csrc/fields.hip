@@ -1,0 +1,212 @@
+// Initialisation, field/total extraction, canonical export and the
+// fixed-order reduction; plus the step-launch dispatcher.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "lbm_device.hpp"
+
+namespace lbmx {
+
+template <typename P> __device__ __forceinline__ const P *pop(const void *base, int i, uint32_t N) {
+    return reinterpret_cast<const P *>(base) + (size_t)i * N;
+}
+template <typename P> __device__ __forceinline__ P *pop_w(void *base, int i, uint32_t N) {
+    return reinterpret_cast<P *>(base) + (size_t)i * N;
+}
+
+// Fixed-order workgroup reduction of K doubles; thread 0 writes dst[0..K-1].
+template <int NT, int K>
+__device__ __forceinline__ void block_totals(double (&v)[K], double *dst) {
+    __shared__ double red[NT / 64][K];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double s = wave_sum(v[k]);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w][k];
+            dst[k] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: f = f^eq(rho,u,T), g = g^eq(T), evaluated in FP64, stored
+// streamed.
+// ---------------------------------------------------------------------------
+template <typename P, int D> __global__ void __launch_bounds__(256) k_init(InitArgs a) {
+    const uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    if (x >= a.N) return;
+    const double uu[3] = {a.u[x], D >= 2 ? a.u[(size_t)a.N + x] : 0.0,
+                          D >= 3 ? a.u[2 * (size_t)a.N + x] : 0.0};
+    const FeqCoef<double> fc = feq_coef<double, D>(a.rho[x], uu, a.T[x]);
+    static_for<0, Lat<D>::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        pop_w<P>(a.f, i, a.N)[x] = (P)feq_dir<double, D, i>(fc);
+    });
+    const GeqCoef<double> gc = geq_coef<double>(a.T[x]);
+    static_for<0, 7>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        pop_w<P>(a.g, j, a.N)[x] = (P)geq_dir<double, j>(gc);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Fields, totals and canonical export (runtime loop over populations).
+// ---------------------------------------------------------------------------
+template <int D> __device__ __forceinline__ uint32_t src_index(const FieldArgs &a, int x, int y, int z,
+                                                              int i, int shift) {
+    const int sx = nb_coord(x, -cx_of(i) * shift, a.n0, a.open0);
+    const int sy = D >= 2 ? nb_coord(y, -cy_of(i) * shift, a.n1, a.open1) : 0;
+    const int sz = D >= 3 ? nb_coord(z, -cz_of(i) * shift, a.n2, a.open2) : 0;
+    return (uint32_t)sx + (uint32_t)a.n0 * ((uint32_t)sy + (uint32_t)a.n1 * (uint32_t)sz);
+}
+
+template <typename P, int D> __global__ void __launch_bounds__(256) k_fields(FieldArgs a) {
+    const uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    const bool valid = x < a.N;
+    const uint32_t xn = valid ? x : a.N - 1;
+    const int cx = xn % a.n0, cy = (xn / a.n0) % a.n1, cz = xn / (a.n0 * a.n1);
+    const int shift = 1 - a.streamed;
+    Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
+    for (int i = 0; i < Lat<D>::Q; ++i) {
+        const double v = (double)pop<P>(a.f, i, a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
+        M.m0 += v;
+        M.m1[0] += cx_of(i) * v;
+        if (D >= 2) M.m1[1] += cy_of(i) * v;
+        if (D >= 3) M.m1[2] += cz_of(i) * v;
+        M.e2 += c2_of<D>(i) * v;
+    }
+    for (int j = 0; j < 7; ++j) M.er += double((j - 3) * (j - 3)) * (double)pop<P>(a.g, j, a.N)[xn];
+    double rho, u[3] = {0.0, 0.0, 0.0}, T, Etot;
+    finish_moments<D>(M, a.n_rot, rho, u, T, Etot);
+    if (valid) {
+        if (a.rho) a.rho[x] = rho;
+        if (a.T) a.T[x] = T;
+        if (a.u)
+            for (int d = 0; d < D; ++d) a.u[(size_t)d * a.N + x] = u[d];
+    }
+    if (a.partials) {
+        double tv[2 + D];
+        tv[0] = valid ? rho : 0.0;
+        for (int d = 0; d < D; ++d) tv[1 + d] = valid ? kR * M.m1[d] : 0.0;
+        tv[1 + D] = valid ? Etot : 0.0;
+        block_totals<256, 2 + D>(tv, a.partials + (size_t)blockIdx.x * (2 + D));
+    }
+}
+
+template <typename P, int D> __global__ void __launch_bounds__(256) k_export(FieldArgs a) {
+    const uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    if (x >= a.N) return;
+    const int cx = x % a.n0, cy = (x / a.n0) % a.n1, cz = x / (a.n0 * a.n1);
+    const int shift = 1 - a.streamed;
+    if (a.f_out)
+        for (int i = 0; i < Lat<D>::Q; ++i)
+            pop_w<P>(a.f_out, i, a.N)[x] = pop<P>(a.f, i, a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
+    if (a.g_out)
+        for (int j = 0; j < 7; ++j) pop_w<P>(a.g_out, j, a.N)[x] = pop<P>(a.g, j, a.N)[x];
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const double *partials, int nparts, int K,
+                                                double *out) {
+    __shared__ double s[256];
+    for (int k = 0; k < K; ++k) {
+        double acc = 0.0;
+        for (int p = threadIdx.x; p < nparts; p += 256) acc += partials[(size_t)p * K + k];
+        s[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = s[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(uint32_t N) { return (N + 255u) / 256u; }
+
+hipError_t launch_init(int dtype, int dim, const InitArgs &a, hipStream_t s) {
+    const dim3 g(blocks_for(a.N)), b(256);
+    if (dtype == 0) {
+        if (dim == 1) hipLaunchKernelGGL((k_init<float, 1>), g, b, 0, s, a);
+        else if (dim == 2) hipLaunchKernelGGL((k_init<float, 2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_init<float, 3>), g, b, 0, s, a);
+    } else {
+        if (dim == 1) hipLaunchKernelGGL((k_init<double, 1>), g, b, 0, s, a);
+        else if (dim == 2) hipLaunchKernelGGL((k_init<double, 2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_init<double, 3>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+int step_ntiles(int dim, const int tile[3], int n0, int n1, int n2, int *t0, int *t1, int *t2) {
+    *t0 = (n0 + tile[0] - 1) / tile[0];
+    *t1 = dim >= 2 ? (n1 + tile[1] - 1) / tile[1] : 1;
+    *t2 = dim >= 3 ? n2 : 1;
+    return *t0 * *t1 * *t2;
+}
+
+bool step_tile_supported(int dtype, int dim, const int tile[3]) {
+    (void)dtype;
+    bool ok = false;
+#define C1(TXv, TYv) ok = ok || (dim == 1 && tile[0] == TXv && tile[1] == 1 && tile[2] == 1);
+#define C2(TXv, TYv) ok = ok || (dim == 2 && tile[0] == TXv && tile[1] == TYv && tile[2] == 1);
+#define C3(TXv, TYv) ok = ok || (dim == 3 && tile[0] == TXv && tile[1] == TYv && tile[2] == 1);
+    LBMX_TILES_1D(C1)
+    LBMX_TILES_2D(C2)
+    LBMX_TILES_3D(C3)
+#undef C1
+#undef C2
+#undef C3
+    return ok;
+}
+
+hipError_t launch_step(int dtype, int dim, const int tile[3], const StepArgs &a, hipStream_t s) {
+    if (dim == 3) return launch_step_3(dtype, tile, a, s);
+    return dtype == 0 ? launch_step_12_f32(dim, tile, a, s) : launch_step_12_f64(dim, tile, a, s);
+}
+
+hipError_t launch_fields(int dtype, int dim, const FieldArgs &a, int *nblocks, hipStream_t s) {
+    const dim3 g(blocks_for(a.N)), b(256);
+    *nblocks = (int)g.x;
+    if (dtype == 0) {
+        if (dim == 1) hipLaunchKernelGGL((k_fields<float, 1>), g, b, 0, s, a);
+        else if (dim == 2) hipLaunchKernelGGL((k_fields<float, 2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_fields<float, 3>), g, b, 0, s, a);
+    } else {
+        if (dim == 1) hipLaunchKernelGGL((k_fields<double, 1>), g, b, 0, s, a);
+        else if (dim == 2) hipLaunchKernelGGL((k_fields<double, 2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_fields<double, 3>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_export(int dtype, int dim, const FieldArgs &a, hipStream_t s) {
+    const dim3 g(blocks_for(a.N)), b(256);
+    if (dtype == 0) {
+        if (dim == 1) hipLaunchKernelGGL((k_export<float, 1>), g, b, 0, s, a);
+        else if (dim == 2) hipLaunchKernelGGL((k_export<float, 2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_export<float, 3>), g, b, 0, s, a);
+    } else {
+        if (dim == 1) hipLaunchKernelGGL((k_export<double, 1>), g, b, 0, s, a);
+        else if (dim == 2) hipLaunchKernelGGL((k_export<double, 2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_export<double, 3>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *partials, int nparts, int K, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, K, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbmx

@@ -45,6 +45,14 @@ struct InitArgs {
 hipError_t launch_init(int dtype, int dim, const InitArgs &a, hipStream_t s);
 // tile = {tx, ty, tz}; returns hipErrorInvalidValue for a shape not compiled.
 hipError_t launch_step(int dtype, int dim, const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step_12_f32(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step_12_f64(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step_3(int dtype, const int tile[3], const StepArgs &a, hipStream_t s);
+
+// Compiled tile shapes (nodes per workgroup along x, y).
+#define LBMX_TILES_1D(X) X(64, 1) X(128, 1) X(256, 1) X(512, 1) X(1024, 1)
+#define LBMX_TILES_2D(X) X(64, 4) X(32, 8) X(128, 2) X(256, 1) X(64, 8) X(32, 16) X(16, 16) X(64, 2)
+#define LBMX_TILES_3D(X) X(64, 1) X(32, 2) X(16, 4)
 bool step_tile_supported(int dtype, int dim, const int tile[3]);
 // Tiles (and therefore partial rows) of a step launch with this tile shape.
 int step_ntiles(int dim, const int tile[3], int n0, int n1, int n2, int *t0, int *t1, int *t2);

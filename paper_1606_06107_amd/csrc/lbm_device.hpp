@@ -148,43 +148,95 @@ template <typename P, int J> __device__ __forceinline__ P geq_dir(const GeqCoef<
 //   nu <  0: nu (-h[+2] + 6 h[+1] - 3 h[0] - 2 h[-1]) / 6
 // ---------------------------------------------------------------------------
 template <typename P> __device__ __forceinline__ P upwind3(P nu, P hm2, P hm1, P h0, P hp1, P hp2) {
-    const P dp = (hm2 - P(6) * hm1 + P(3) * h0 + P(2) * hp1) / P(6);
-    const P dm = (-hp2 + P(6) * hp1 - P(3) * h0 - P(2) * hm1) / P(6);
+    const P dp = (hm2 - P(6) * hm1 + P(3) * h0 + P(2) * hp1) * P(1.0 / 6.0);
+    const P dm = (-hp2 + P(6) * hp1 - P(3) * h0 - P(2) * hm1) * P(1.0 / 6.0);
     return nu * (nu >= P(0) ? dp : dm);
 }
 
+// Periodic wrap or clamp of an arbitrary coordinate (tile halos may reach
+// more than one period past the edge of a small grid).
+__device__ __forceinline__ int wrap_any(int s, int n, int open) {
+    if (open) return s < 0 ? 0 : (s >= n ? n - 1 : s);
+    s %= n;
+    return s < 0 ? s + n : s;
+}
+
+// Load/store population i at a 32-bit byte offset from the population's
+// (uniform) base address: lets the compiler use SGPR-base + VGPR-offset
+// addressing.  Requires N * sizeof(P) < 2^32.
+template <typename P> __device__ __forceinline__ P ldp(const void *base, int i, uint32_t N,
+                                                      uint32_t off) {
+    const char *p = reinterpret_cast<const char *>(base) + (size_t)i * N * sizeof(P);
+    return *reinterpret_cast<const P *>(p + off);
+}
+template <typename P> __device__ __forceinline__ void stp(void *base, int i, uint32_t N,
+                                                         uint32_t off, P v) {
+    char *p = reinterpret_cast<char *>(base) + (size_t)i * N * sizeof(P);
+    *reinterpret_cast<P *>(p + off) = v;
+}
+
+// Equilibrium of the direction pair (c, -c): with a = c.ru,
+//   f^eq(+-c) / (w rho) = E(a^2) +- a O(a^2),  E = P0 + a^2 (P2 + a^2/24),
+//   O = P1 + a^2/6   (same polynomial as feq_dir).
+template <typename P, int D, int I>
+__device__ __forceinline__ void feq_pair(const FeqCoef<P> &c, P &fplus, P &fminus) {
+    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+    constexpr double xi2d = kR * kR * c2_of<D>(I);
+    const P xi2 = P(xi2d);
+    P a = P(cx) * c.ru[0];
+    if constexpr (D >= 2 && cy != 0) a += P(cy) * c.ru[1];
+    if constexpr (D >= 3 && cz != 0) a += P(cz) * c.ru[2];
+    const P a2 = a * a;
+    const P p0 = c.A0 + xi2 * (c.A1 + xi2 * c.A2);
+    const P p1 = c.B0 + xi2 * c.B1;
+    const P p2 = c.C0 + xi2 * c.C1;
+    const P E = p0 + a2 * (p2 + a2 * P(1.0 / 24.0));
+    const P O = (p1 + a2 * P(1.0 / 6.0)) * a;
+    const P wr = P(w_of<D>(I)) * c.rho;
+    fplus = wr * (E + O);
+    fminus = wr * (E - O);
+}
+
 // ---------------------------------------------------------------------------
-// Conservative FP32 relaxation.  The BGK increment d_i = omega (f^eq_i - f_i)
-// conserves mass and momentum and moves sum_i |c_i|^2 f_i by
-// omega (rho (|u|^2 + D T) / r^2 - e2) (integer-c units) in exact
+// Conservative FP32 relaxation.  The BGK increments d_i = omega (f^eq_i - f_i)
+// conserve mass and momentum and move sum_i |c_i|^2 f_i by
+// t2 = omega (rho (|u|^2 + D T) / r^2 - e2) (integer-c units) in exact
 // arithmetic.  In FP32 the rounded weights and polynomial bias these sums by
-// ~1e-8 per step, which accumulates over thousands of steps.  The sums of
-// the FP32 increments are taken in FP64 and the defects (d0, d1, d2) are
-// removed with the increment w_i (alpha + beta.c_i + gamma |c_i|^2), using
-// the lattice moments sum w = 1, sum w c_a c_b = delta_ab / r^2,
-// sum w |c|^4 = D (D+2) / r^4.  In exact arithmetic the defects are zero.
+// ~1e-8 rho per step, which accumulates over thousands of steps.  The
+// increments of all populations are summed; the defects
+//   R0 = -sum d,  R1 = -sum c d,  R2 = t2 - sum |c|^2 d
+// are then added to the 2D+1 populations with |c| <= 1 (rest and +-e_a),
+// which are stored last:
+//   eps_rest = R0 - R2,  eps_{+-e_a} = R2 / (2D) +- R1_a / 2,
+// so the stored increments have exactly the target sums up to the final
+// (unbiased) rounding of the stored values.  In exact arithmetic eps = 0.
 // ---------------------------------------------------------------------------
-struct Fix {
-    double alpha, beta[3], gamma;
+template <int D> __host__ __device__ constexpr int special_rank(int i) {
+    // 0 = rest, 1 + 2a = -e_a, 2 + 2a = +e_a, -1 = not special
+    constexpr int H = Lat<D>::Q / 2;
+    if (i == H) return 0;
+    int p = 1;
+    for (int a = 0; a < D; ++a, p *= 7) {
+        if (i == H - p) return 1 + 2 * a;
+        if (i == H + p) return 2 + 2 * a;
+    }
+    return -1;
+}
+struct Eps {
+    double e[7];  // indexed by special_rank
 };
-template <int D> __device__ __forceinline__ Fix fix_from_defects(double d0, const double d1[3],
-                                                                 double d2) {
-    constexpr double r2 = kR * kR;
-    Fix x;
-    x.gamma = (d2 - d0 * D / r2) * r2 * r2 / (2.0 * D);
-    x.alpha = d0 - x.gamma * D / r2;
+template <int D> __device__ __forceinline__ Eps eps_from_defects(double R0, const double R1[3],
+                                                                 double R2) {
+    Eps x;
+    x.e[0] = R0 - R2;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x.beta[a] = a < D ? r2 * d1[a] : 0.0;
+    for (int a = 0; a < 3; ++a) {
+        x.e[1 + 2 * a] = a < D ? R2 / (2.0 * D) - 0.5 * R1[a] : 0.0;
+        x.e[2 + 2 * a] = a < D ? R2 / (2.0 * D) + 0.5 * R1[a] : 0.0;
+    }
     return x;
 }
-template <typename P, int D, int I> __device__ __forceinline__ P fix_dir(P alpha, const P beta[3],
-                                                                        P gamma) {
-    P v = alpha + P(c2_of<D>(I)) * gamma;
-    if constexpr (cx_of(I) != 0) v += P(cx_of(I)) * beta[0];
-    if constexpr (D >= 2 && cy_of(I) != 0) v += P(cy_of(I)) * beta[1];
-    if constexpr (D >= 3 && cz_of(I) != 0) v += P(cz_of(I)) * beta[2];
-    return P(w_of<D>(I)) * v;
-}
+
 // Rotational analogue on D1Q7 with sum w j^2 = 1/r^2, sum w j^4 = 3/r^4:
 // increment w_j (alpha + gamma j^2) removes the defects of sum_j and sum_j j^2.
 __device__ __forceinline__ void gfix_from_defects(double d0, double d2, double &alpha,

@@ -1,0 +1,448 @@
+// Per-time-step kernels of the decoupled Hermite lattice Boltzmann scheme on
+// D1Q7^D (D = 1, 2, 3) translational and D1Q7 rotational populations.
+//
+// One launch = one time step of Sec. V B of the paper, fused:
+//   gather the streamed f(x, t) = f*(S(x - c_i), t-1)   (pull; S = wrap/clamp)
+//   FP64 moments rho, rho u, E_t, e_r and the temperature T   (steps 3-4)
+//   fourth-order Hermite equilibria f^eq(rho,u,T), g^eq(T)     (Sec. IV)
+//   BGK relaxation of f; the post-collision f*(x, t) is stored in place of x
+//   forward-Euler third-order-upwind advection of g with u, plus relaxation
+//   (Sec. V A), g(x, t+1) stored
+//   optional per-tile FP64 totals of time t (mass, momentum, energy)
+// Populations are SoA [Q][N], node index x fastest.  Right after
+// initialisation f is stored streamed (`streamed` = 1, read in place).
+//
+// Kernel templates, included by the step_*.hip translation units that
+// instantiate and launch them.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "lbm_device.hpp"
+
+namespace lbmx {
+
+template <typename P> __device__ __forceinline__ const P *pop(const void *base, int i, uint32_t N) {
+    return reinterpret_cast<const P *>(base) + (size_t)i * N;
+}
+template <typename P> __device__ __forceinline__ P *pop_w(void *base, int i, uint32_t N) {
+    return reinterpret_cast<P *>(base) + (size_t)i * N;
+}
+
+// Fixed-order workgroup reduction of K doubles; thread 0 writes dst[0..K-1].
+template <int NT, int K>
+__device__ __forceinline__ void block_totals(double (&v)[K], double *dst) {
+    __shared__ double red[NT / 64][K];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double s = wave_sum(v[k]);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w][k];
+            dst[k] = s;
+        }
+    }
+}
+
+// Rotational update g' = g - adv - omega (g - g^eq(T)), stored at byte
+// offset `off`.  For FP32 the relaxation increments r_j = omega (g^eq_j - g_j)
+// are corrected so that sum_j r_j = omega (1 - sum g) and
+// sum_j j^2 r_j = omega (T/r^2 - sum j^2 g) hold to FP64 rounding (see
+// gfix_from_defects).
+template <typename P>
+__device__ __forceinline__ void rot_relax_store(const P (&gv)[7], const P (&adv)[7],
+                                                const GeqCoef<P> &gc, P om, double omega,
+                                                double T, double er, bool valid, void *g_out,
+                                                uint32_t N, uint32_t off) {
+    if constexpr (sizeof(P) == 4) {
+        double s0 = 0.0, s2 = 0.0, g0 = 0.0;
+        P rl[7];
+        static_for<0, 7>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            rl[j] = om * (geq_dir<P, j>(gc) - gv[j]);
+            s0 += (double)rl[j];
+            g0 += (double)gv[j];
+            if constexpr (j != 3) s2 += double((j - 3) * (j - 3)) * (double)rl[j];
+        });
+        double al, ga;
+        gfix_from_defects(omega * (1.0 - g0) - s0, omega * (T / (kR * kR) - er) - s2, al, ga);
+        const P alp = (P)al, gam = (P)ga;
+        static_for<0, 7>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const P fixj = P(kW1[iabs(j - 3)]) * (alp + P((j - 3) * (j - 3)) * gam);
+            const P gn = gv[j] - adv[j] + (rl[j] + fixj);
+            if (valid) stp<P>(g_out, j, N, off, gn);
+        });
+    } else {
+        static_for<0, 7>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const P gn = gv[j] - adv[j] - om * (gv[j] - geq_dir<P, j>(gc));
+            if (valid) stp<P>(g_out, j, N, off, gn);
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// D = 1, 2: one node per thread, all Q populations in registers.
+// ---------------------------------------------------------------------------
+template <typename P, int D, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY, sizeof(P) == 4 ? 4 : 2) k_step_12(StepArgs a) {
+    constexpr int Q = Lat<D>::Q;
+    constexpr int H = Q / 2;  // rest direction c = 0; pairs (i, Q-1-i) for i < H
+    constexpr int NT = TX * TY;
+    constexpr int NS = 2 * D + 1;  // populations absorbing the FP32 defects
+    constexpr uint32_t SZ = sizeof(P);
+    constexpr bool F32 = sizeof(P) == 4;
+
+    const int tile = xcd_tile(blockIdx.x, a.ntiles);
+    const int x0 = (tile % a.tiles0) * TX;
+    const int y0 = D >= 2 ? (tile / a.tiles0) * TY : 0;
+    const int lx = threadIdx.x % TX, ly = D >= 2 ? threadIdx.x / TX : 0;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool valid = x < a.n0 && (D < 2 || y < a.n1);
+    const int xc = x < a.n0 ? x : a.n0 - 1;
+    const int yc = D >= 2 ? (y < a.n1 ? y : a.n1 - 1) : 0;
+    const uint32_t N = a.N;
+    const uint32_t nodeb = ((uint32_t)xc + (uint32_t)a.n0 * (uint32_t)yc) * SZ;
+    const int shift = 1 - a.streamed;
+
+    // 1. Gather the streamed populations f_i(x) = f*_i(S(x - c_i)) (pull).
+    uint32_t ox[7], oy[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        ox[k] = (uint32_t)nb_coord(xc, -(k - 3) * shift, a.n0, a.open0) * SZ;
+        oy[k] = D >= 2 ? (uint32_t)nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * (uint32_t)a.n0 * SZ
+                       : 0u;
+    }
+    P fv[Q];
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        fv[i] = ldp<P>(a.f_in, i, N, ox[cx_of(i) + 3] + (D >= 2 ? oy[cy_of(i) + 3] : 0u));
+    });
+    P gv[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) gv[j] = ldp<P>(a.g_in, j, N, nodeb);
+
+    // 2. FP64 moments via per-column (cx) and per-row (cy) sums.
+    double col[7] = {0, 0, 0, 0, 0, 0, 0}, row[7] = {0, 0, 0, 0, 0, 0, 0};
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const double v = (double)fv[i];
+        col[cx_of(i) + 3] += v;
+        if constexpr (D >= 2) row[cy_of(i) + 3] += v;
+    });
+    Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const double c = k - 3;
+        M.m0 += col[k];
+        M.m1[0] += c * col[k];
+        M.e2 += c * c * col[k];
+        if constexpr (D >= 2) {
+            M.m1[1] += c * row[k];
+            M.e2 += c * c * row[k];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        if (j != 3) M.er += double((j - 3) * (j - 3)) * (double)gv[j];
+    double rho, u[3] = {0.0, 0.0, 0.0}, T, Etot;
+    finish_moments<D>(M, a.n_rot, rho, u, T, Etot);
+
+    if (a.partials) {  // uniform branch: totals of time t
+        double tv[2 + D];
+        tv[0] = valid ? rho : 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) tv[1 + d] = valid ? kR * M.m1[d] : 0.0;
+        tv[1 + D] = valid ? Etot : 0.0;
+        block_totals<NT, 2 + D>(tv, a.partials + (size_t)tile * (2 + D));
+    }
+
+    // 3. BGK relaxation towards the Hermite equilibrium; store post-collision.
+    const P up[3] = {(P)u[0], (P)u[1], (P)u[2]};
+    const FeqCoef<P> fc = feq_coef<P, D>((P)rho, up, (P)T);
+    const P om = (P)a.omega;
+    P dsp[NS];                               // increments of the special populations
+    P cs[7] = {0, 0, 0, 0, 0, 0, 0}, rs[7] = {0, 0, 0, 0, 0, 0, 0};  // FP32 sums
+    auto relax = [&](auto I, P fe) {
+        constexpr int i = decltype(I)::value;
+        constexpr int sr = special_rank<D>(i);
+        const P d = om * (fe - fv[i]);
+        if constexpr (F32) {
+            cs[cx_of(i) + 3] += d;
+            if constexpr (D >= 2) rs[cy_of(i) + 3] += d;
+        }
+        if constexpr (F32 && sr >= 0) dsp[sr] = d;
+        else if (valid) stp<P>(a.f_out, i, N, nodeb, fv[i] + d);
+    };
+    static_for<0, H>([&](auto I) {
+        constexpr int i = decltype(I)::value, k = Q - 1 - i;
+        P fp, fm;
+        feq_pair<P, D, i>(fc, fp, fm);
+        relax(Int<i>{}, fp);
+        relax(Int<k>{}, fm);
+    });
+    relax(Int<H>{}, P(w_of<D>(H)) * fc.rho * fc.A0);
+    if constexpr (F32) {
+        double S0 = 0.0, S1[3] = {0.0, 0.0, 0.0}, S2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const double c = k - 3, vc = (double)cs[k];
+            S0 += vc;
+            S1[0] += c * vc;
+            S2 += c * c * vc;
+            if constexpr (D >= 2) {
+                const double vr = (double)rs[k];
+                S1[1] += c * vr;
+                S2 += c * c * vr;
+            }
+        }
+        const double mm = M.m1[0] * M.m1[0] + (D >= 2 ? M.m1[1] * M.m1[1] : 0.0);
+        const double t2 = a.omega * (mm / rho + D * rho * T / (kR * kR) - M.e2);
+        const double R1[3] = {-S1[0], -S1[1], 0.0};
+        const Eps ep = eps_from_defects<D>(-S0, R1, t2 - S2);
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int sr = special_rank<D>(i);
+            if constexpr (sr >= 0)
+                if (valid) stp<P>(a.f_out, i, N, nodeb, fv[i] + (dsp[sr] + (P)ep.e[sr]));
+        });
+    }
+
+    // 4. Rotational populations: upwind advection with u (cached stencil
+    //    loads), relaxation to g^eq(T).
+    const GeqCoef<P> gc = geq_coef<P>((P)T);
+    const P nu0 = up[0] * P(1.0 / kR), nu1 = up[1] * P(1.0 / kR);
+    uint32_t gxo[5], gyo[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        gxo[k] = ((uint32_t)nb_coord(xc, k - 2, a.n0, a.open0) + (uint32_t)a.n0 * (uint32_t)yc) * SZ;
+        gyo[k] = D >= 2 ? ((uint32_t)xc + (uint32_t)a.n0 * (uint32_t)nb_coord(yc, k - 2, a.n1, a.open1)) * SZ
+                        : 0u;
+    }
+    P adv[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        adv[j] = upwind3<P>(nu0, ldp<P>(a.g_in, j, N, gxo[0]), ldp<P>(a.g_in, j, N, gxo[1]), gv[j],
+                            ldp<P>(a.g_in, j, N, gxo[3]), ldp<P>(a.g_in, j, N, gxo[4]));
+        if constexpr (D >= 2)
+            adv[j] += upwind3<P>(nu1, ldp<P>(a.g_in, j, N, gyo[0]), ldp<P>(a.g_in, j, N, gyo[1]), gv[j],
+                                 ldp<P>(a.g_in, j, N, gyo[3]), ldp<P>(a.g_in, j, N, gyo[4]));
+    }
+    rot_relax_store<P>(gv, adv, gc, om, a.omega, T, M.er, valid, a.g_out, N, nodeb);
+}
+
+// ---------------------------------------------------------------------------
+// D = 3: D3Q343 has too many populations for one thread's registers.  A
+// workgroup of four waves serves 64 nodes; wave w owns a quarter of the
+// populations (and two of the seven rotational ones).  Each wave accumulates
+// partial FP64 moments of its populations, the partials meet in LDS and are
+// summed in a fixed order, every wave derives the same rho, u, T, and then
+// relaxes and stores the populations it holds in registers.
+// ---------------------------------------------------------------------------
+constexpr int kQ3 = 343;
+constexpr int kSplit3 = 86;  // populations per wave: 86, 86, 86, 85
+
+template <typename P, int W>
+__device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7], const int (&sy)[7],
+                                           const int (&sz)[7], uint32_t node, int xc, int yc,
+                                           int zc, bool valid, int tile, double (*part)[64][6],
+                                           double (*part2)[64][8]) {
+    constexpr int LO = W * kSplit3;
+    constexpr int HI = (W + 1) * kSplit3 < kQ3 ? (W + 1) * kSplit3 : kQ3;
+    constexpr bool F32 = sizeof(P) == 4;
+    const uint32_t N = a.N;
+    const int lane = threadIdx.x & 63;
+    P fv[HI - LO];
+    double m0 = 0.0, mx = 0.0, my = 0.0, mz = 0.0, e2 = 0.0, er = 0.0;
+    static_for<LO, HI>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const uint32_t idx = (uint32_t)(sx[cx_of(i) + 3] + sy[cy_of(i) + 3] + sz[cz_of(i) + 3]);
+        const P f = pop<P>(a.f_in, i, N)[idx];
+        fv[i - LO] = f;
+        const double v = (double)f;
+        m0 += v;
+        if constexpr (cx_of(i) != 0) mx += double(cx_of(i)) * v;
+        if constexpr (cy_of(i) != 0) my += double(cy_of(i)) * v;
+        if constexpr (cz_of(i) != 0) mz += double(cz_of(i)) * v;
+        if constexpr (c2_of<3>(i) != 0) e2 += double(c2_of<3>(i)) * v;
+    });
+    // rotational populations j = W and j = W + 4 (if < 7)
+    constexpr int J0 = W, J1 = W + 4;
+    constexpr bool HAS1 = J1 < 7;
+    const P g0 = pop<P>(a.g_in, J0, N)[node];
+    P g1 = P(0);
+    if constexpr (HAS1) g1 = pop<P>(a.g_in, J1, N)[node];
+    er += double((J0 - 3) * (J0 - 3)) * (double)g0;
+    if constexpr (HAS1) er += double((J1 - 3) * (J1 - 3)) * (double)g1;
+
+    part[W][lane][0] = m0;
+    part[W][lane][1] = mx;
+    part[W][lane][2] = my;
+    part[W][lane][3] = mz;
+    part[W][lane][4] = e2;
+    part[W][lane][5] = er;
+    __syncthreads();
+    Mom M;
+    M.m0 = part[0][lane][0] + part[1][lane][0] + part[2][lane][0] + part[3][lane][0];
+    M.m1[0] = part[0][lane][1] + part[1][lane][1] + part[2][lane][1] + part[3][lane][1];
+    M.m1[1] = part[0][lane][2] + part[1][lane][2] + part[2][lane][2] + part[3][lane][2];
+    M.m1[2] = part[0][lane][3] + part[1][lane][3] + part[2][lane][3] + part[3][lane][3];
+    M.e2 = part[0][lane][4] + part[1][lane][4] + part[2][lane][4] + part[3][lane][4];
+    M.er = part[0][lane][5] + part[1][lane][5] + part[2][lane][5] + part[3][lane][5];
+    double rho, u[3], T, Etot;
+    finish_moments<3>(M, a.n_rot, rho, u, T, Etot);
+
+    if constexpr (W == 0) {
+        if (a.partials) {  // one wave holds all 64 nodes of the tile
+            double t[5] = {valid ? rho : 0.0, valid ? kR * M.m1[0] : 0.0,
+                           valid ? kR * M.m1[1] : 0.0, valid ? kR * M.m1[2] : 0.0,
+                           valid ? Etot : 0.0};
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const double s = wave_sum(t[k]);
+                if (lane == 0) a.partials[(size_t)tile * 5 + k] = s;
+            }
+        }
+    }
+
+    const P up[3] = {(P)u[0], (P)u[1], (P)u[2]};
+    const FeqCoef<P> fc = feq_coef<P, 3>((P)rho, up, (P)T);
+    const GeqCoef<P> gc = geq_coef<P>((P)T);
+    const P om = (P)a.omega;
+
+    // Rotational advection for the wave's j's: 3-D upwind stencil from global.
+    const P nu[3] = {up[0] / P(kR), up[1] / P(kR), up[2] / P(kR)};
+    const uint32_t sxy = (uint32_t)a.n0 * (uint32_t)a.n1;
+    auto advect = [&](auto JJ, P gcen) -> P {
+        constexpr int j = decltype(JJ)::value;
+        const P *gj = pop<P>(a.g_in, j, N);
+        P h[5];
+        P adv = P(0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            h[k] = (k == 2) ? gcen : gj[nb_coord(xc, k - 2, a.n0, a.open0) + a.n0 * yc + sxy * zc];
+        adv += upwind3<P>(nu[0], h[0], h[1], h[2], h[3], h[4]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            h[k] = (k == 2) ? gcen : gj[xc + a.n0 * nb_coord(yc, k - 2, a.n1, a.open1) + sxy * zc];
+        adv += upwind3<P>(nu[1], h[0], h[1], h[2], h[3], h[4]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            h[k] = (k == 2) ? gcen : gj[xc + a.n0 * yc + sxy * nb_coord(zc, k - 2, a.n2, a.open2)];
+        adv += upwind3<P>(nu[2], h[0], h[1], h[2], h[3], h[4]);
+        return adv;
+    };
+    const P adv0 = advect(Int<J0>{}, g0);
+    P adv1 = P(0);
+    if constexpr (HAS1) adv1 = advect(Int<J1 < 7 ? J1 : 0>{}, g1);
+
+    // BGK increments of this wave's populations; all but the special ones
+    // (rest, +-e_a) are stored at once.  FP32: the increments' sums meet in
+    // LDS and the defects go to the special populations (eps_from_defects).
+    constexpr int NSP = 7;
+    P dsp[NSP];
+    P s0 = P(0), s1x = P(0), s1y = P(0), s1z = P(0), s2 = P(0);
+    static_for<LO, HI>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int sr = special_rank<3>(i);
+        const P d = om * (feq_dir<P, 3, i>(fc) - fv[i - LO]);
+        if constexpr (F32) {
+            s0 += d;
+            if constexpr (cx_of(i) != 0) s1x += P(cx_of(i)) * d;
+            if constexpr (cy_of(i) != 0) s1y += P(cy_of(i)) * d;
+            if constexpr (cz_of(i) != 0) s1z += P(cz_of(i)) * d;
+            if constexpr (c2_of<3>(i) != 0) s2 += P(c2_of<3>(i)) * d;
+        }
+        if constexpr (F32 && sr >= 0) dsp[sr] = d;
+        else if (valid) pop_w<P>(a.f_out, i, N)[node] = fv[i - LO] + d;
+    });
+    P gal = P(0), gga = P(0);
+    if constexpr (F32) {
+        double rs0 = (double)(om * (geq_dir<P, J0>(gc) - g0));
+        double rs2 = double((J0 - 3) * (J0 - 3)) * rs0;
+        double gs = (double)g0;
+        if constexpr (HAS1) {
+            const double r1 = (double)(om * (geq_dir<P, J1 < 7 ? J1 : 0>(gc) - g1));
+            rs0 += r1;
+            rs2 += double((J1 - 3) * (J1 - 3)) * r1;
+            gs += (double)g1;
+        }
+        part2[W][lane][0] = (double)s0;
+        part2[W][lane][1] = (double)s1x;
+        part2[W][lane][2] = (double)s1y;
+        part2[W][lane][3] = (double)s1z;
+        part2[W][lane][4] = (double)s2;
+        part2[W][lane][5] = rs0;
+        part2[W][lane][6] = rs2;
+        part2[W][lane][7] = gs;
+        __syncthreads();
+        double S[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            S[k] = part2[0][lane][k] + part2[1][lane][k] + part2[2][lane][k] + part2[3][lane][k];
+        const double mm = M.m1[0] * M.m1[0] + M.m1[1] * M.m1[1] + M.m1[2] * M.m1[2];
+        const double t2 = a.omega * (mm / rho + 3.0 * rho * T / (kR * kR) - M.e2);
+        const double R1[3] = {-S[1], -S[2], -S[3]};
+        const Eps ep = eps_from_defects<3>(-S[0], R1, t2 - S[4]);
+        static_for<LO, HI>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int sr = special_rank<3>(i);
+            if constexpr (sr >= 0)
+                if (valid) pop_w<P>(a.f_out, i, N)[node] = fv[i - LO] + (dsp[sr] + (P)ep.e[sr]);
+        });
+        double ga_d, ga_g;
+        gfix_from_defects(a.omega * (1.0 - S[7]) - S[5], a.omega * (T / (kR * kR) - M.er) - S[6],
+                          ga_d, ga_g);
+        gal = (P)ga_d;
+        gga = (P)ga_g;
+    }
+    auto relax_store = [&](auto JJ, P gcen, P adv) {
+        constexpr int j = decltype(JJ)::value;
+        const P rl = om * (geq_dir<P, j>(gc) - gcen);
+        P gn;
+        if constexpr (F32)
+            gn = gcen - adv + (rl + P(kW1[iabs(j - 3)]) * (gal + P((j - 3) * (j - 3)) * gga));
+        else gn = gcen - adv + rl;
+        if (valid) pop_w<P>(a.g_out, j, N)[node] = gn;
+    };
+    relax_store(Int<J0>{}, g0, adv0);
+    if constexpr (HAS1) relax_store(Int<J1 < 7 ? J1 : 0>{}, g1, adv1);
+}
+
+template <typename P, int TX, int TY>
+__global__ void __launch_bounds__(256) k_step_3(StepArgs a) {
+    static_assert(TX * TY == 64, "64 nodes per workgroup");
+    __shared__ double part[4][64][6];
+    __shared__ double part2[4][64][8];
+    const int tile = xcd_tile(blockIdx.x, a.ntiles);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t0 = tile % a.tiles0, rest = tile / a.tiles0;
+    const int t1 = rest % a.tiles1, t2 = rest / a.tiles1;
+    const int x = t0 * TX + lane % TX, y = t1 * TY + lane / TX, z = t2;
+    const bool valid = x < a.n0 && y < a.n1 && z < a.n2;
+    const int xc = x < a.n0 ? x : a.n0 - 1, yc = y < a.n1 ? y : a.n1 - 1, zc = z;
+    const uint32_t node = (uint32_t)xc + (uint32_t)a.n0 * ((uint32_t)yc + (uint32_t)a.n1 * zc);
+    const int shift = 1 - a.streamed;
+    int sx[7], sy[7], sz[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        sx[k] = nb_coord(xc, -(k - 3) * shift, a.n0, a.open0);
+        sy[k] = nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * a.n0;
+        sz[k] = nb_coord(zc, -(k - 3) * shift, a.n2, a.open2) * (a.n0 * a.n1);
+    }
+    switch (w) {  // wave-uniform
+        case 0: step3_wave<P, 0>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
+        case 1: step3_wave<P, 1>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
+        case 2: step3_wave<P, 2>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
+        default: step3_wave<P, 3>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
+    }
+}
+
+}  // namespace lbmx
