@@ -1,0 +1,92 @@
+"""Python front end of the batched shock tubes (lbm_batch_init /
+lbm_batch_step / lbm_batch_moments): many independent 1-D D1Q7 + D1Q7 tubes
+of uneven length, per-instance n, tau and step count, advanced by one
+persistent launch.  PyTorch provides device memory and the stream."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Batch:
+    """lengths[I] (>= 1 each), n_rot[I], tau[I], nsteps[I] (per call of
+    step()).  block/chunk/superstep: launch shape (0 = library default;
+    chosen by the autotuner)."""
+
+    def __init__(self, lengths, n_rot, tau, nsteps, dtype=torch.float32, device="cuda",
+                 block=0, chunk=0, superstep=0, stream=None):
+        self.lib = L.load()
+        dev = torch.device(device)
+        lengths = np.asarray(lengths, dtype=np.int64)
+        self.I = len(lengths)
+        self.offsets_h = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+        self.total = int(self.offsets_h[-1])
+        self.dtype, self.device = dtype, dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.offsets = torch.as_tensor(self.offsets_h, device=dev)
+        self.n_rot = torch.as_tensor(np.asarray(n_rot, dtype=np.float64), device=dev)
+        self.tau = torch.as_tensor(np.asarray(tau, dtype=np.float64), device=dev)
+        self.nsteps = torch.as_tensor(np.asarray(nsteps, dtype=np.int64), device=dev)
+        self.f = [torch.empty((7, self.total), dtype=dtype, device=dev) for _ in range(2)]
+        self.g = [torch.empty((7, self.total), dtype=dtype, device=dev) for _ in range(2)]
+        self.status = torch.full((self.I,), -1, dtype=torch.int32, device=dev)
+        d = L.LbmBatchDesc()
+        d.abi_version = L.LBM_ABI_VERSION
+        d.dtype = L.LBM_F32 if dtype == torch.float32 else L.LBM_F64
+        d.num_instances = self.I
+        d.total_nodes = self.total
+        d.offsets = self.offsets.data_ptr()
+        d.n_rot = self.n_rot.data_ptr()
+        d.tau = self.tau.data_ptr()
+        d.nsteps = self.nsteps.data_ptr()
+        for k in range(2):
+            d.f[k] = self.f[k].data_ptr()
+            d.g[k] = self.g[k].data_ptr()
+        d.status = self.status.data_ptr()
+        d.block, d.chunk, d.superstep = int(block), int(chunk), int(superstep)
+        nbytes = self.lib.lbm_batch_workspace_bytes(ctypes.byref(d))
+        self.workspace = torch.empty(max(nbytes, 256) // 4 + 64, dtype=torch.int32, device=dev)
+        d.workspace = self.workspace.data_ptr()
+        self.desc = d
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def init(self, rho, u, T):
+        """Equilibrium initial state from packed FP64 fields (length total)."""
+        self._fields = [torch.as_tensor(np.asarray(a, dtype=np.float64).reshape(-1)).to(self.device)
+                        for a in (rho, u, T)]
+        r, u_, T_ = self._fields
+        assert r.numel() == self.total and u_.numel() == self.total and T_.numel() == self.total
+        L.check(self.lib.lbm_batch_init(ctypes.byref(self.desc), _p(r), _p(u_), _p(T_), self._s()))
+        return self
+
+    def set_nsteps(self, nsteps):
+        self.nsteps.copy_(torch.as_tensor(np.asarray(nsteps, dtype=np.int64)))
+
+    def step(self):
+        """Advance every tube i by nsteps[i] steps (one persistent launch)."""
+        L.check(self.lib.lbm_batch_step(ctypes.byref(self.desc), self._s()))
+        return self
+
+    def moments(self):
+        """Packed FP64 (rho, u, T) device tensors of the current state."""
+        dev = self.device
+        r = torch.empty(self.total, dtype=torch.float64, device=dev)
+        u = torch.empty(self.total, dtype=torch.float64, device=dev)
+        T = torch.empty(self.total, dtype=torch.float64, device=dev)
+        L.check(self.lib.lbm_batch_moments(ctypes.byref(self.desc), _p(r), _p(u), _p(T), self._s()))
+        return r, u, T
+
+    def split(self, packed):
+        """Host list of per-tube arrays from a packed device or host array."""
+        a = packed.cpu().numpy() if torch.is_tensor(packed) else np.asarray(packed)
+        return [a[..., self.offsets_h[i]:self.offsets_h[i + 1]] for i in range(self.I)]

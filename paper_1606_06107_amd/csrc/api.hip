@@ -113,6 +113,10 @@ lbm_status validate(const lbm_desc *d) {
 
 }  // namespace
 
+namespace lbmx {
+void set_error(const char *msg) { g_err = msg; }
+}  // namespace lbmx
+
 struct lbm_sim_s {
     lbm_desc d;
     hipStream_t stream;    // caller's stream

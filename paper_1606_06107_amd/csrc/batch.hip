@@ -1,14 +1,545 @@
-// Batched shock tubes (declared in include/lbm.h).
+// Batched 1-D shock tubes (declared in include/lbm.h): many independent
+// D1Q7 + D1Q7 tubes of uneven length, each with its own n, tau and number of
+// steps, both ends open (zero-gradient clamp), advanced by ONE persistent
+// launch.
+//
+// Work distribution: a one-workgroup bitonic sort orders the tubes by work
+// (length x steps, longest first); persistent workgroups pop tubes from a
+// device counter in that order (longest-processing-time-first list
+// scheduling) and exit when the queue is empty.
+//
+// On-chip time loop: a tube of length L <= C (C = chunk capacity in nodes)
+// is loaded into LDS once, advanced through all its steps there (two
+// workgroup barriers per step) and written back.  A longer tube advances in
+// passes of S steps: each pass walks the tube in chunks of C - 6S interior
+// nodes plus 3S halo nodes per side (the update reaches 3 nodes per step),
+// reads the pass's input buffer and writes the interior to the other buffer.
+// The number of passes is even, so the result ends in f[0], g[0].
+//
+// Per node and step the arithmetic is that of the per-step kernels (Sec. V
+// B): FP64 moments and temperature, fourth-order Hermite equilibria, BGK
+// with the conservative FP32 correction, third-order upwind advection of the
+// rotational populations.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
 #include "lbm.h"
+#include "lbm_device.hpp"
+
+namespace lbmx {
+
+struct BatchArgs {
+    const int64_t *offsets;
+    const double *n_rot, *tau;
+    const int64_t *nsteps;
+    void *f[2], *g[2];  // packed [7][total]
+    int32_t *status;
+    int32_t *order;     // workspace: processing order
+    int32_t *counter;   // workspace: queue head
+    int num;
+    uint32_t total;
+    int chunk;      // nodes per LDS buffer
+    int superstep;  // steps per pass of a chunked tube
+};
+
+// ---------------------------------------------------------------------------
+// Longest-work-first order: bitonic sort (descending) of 64-bit keys
+// (work << 24 | (2^24 - 1 - index)) in LDS by one workgroup; also resets the
+// queue head.  num <= kSortMax; larger batches keep index order.
+// ---------------------------------------------------------------------------
+constexpr int kSortMax = 16384;
+
+__global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
+    __shared__ unsigned long long key[kSortMax];
+    const int n = a.num;
+    if (threadIdx.x == 0) *a.counter = 0;
+    if (n > kSortMax) {
+        for (int i = threadIdx.x; i < n; i += 1024) a.order[i] = i;
+        return;
+    }
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    for (int i = threadIdx.x; i < P2; i += 1024) {
+        unsigned long long k = 0;
+        if (i < n) {
+            const long long L = a.offsets[i + 1] - a.offsets[i];
+            long long w = L * (a.nsteps[i] > 0 ? a.nsteps[i] : 0);
+            if (w > (1LL << 39) - 1) w = (1LL << 39) - 1;
+            k = ((unsigned long long)w << 24) | (unsigned long long)((1 << 24) - 1 - i);
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P2; i += 1024) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool desc = (i & size) == 0;
+                    const unsigned long long ki = key[i], kj = key[j];
+                    if (desc ? (ki < kj) : (ki > kj)) {
+                        key[i] = kj;
+                        key[j] = ki;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += 1024)
+        a.order[i] = (1 << 24) - 1 - (int)(key[i] & ((1ULL << 24) - 1));
+}
+
+// ---------------------------------------------------------------------------
+// One node's update from LDS (region of R nodes, local clamp at the region
+// edges).  F, G: [7][C] arrays; shift = 0 if F holds streamed populations,
+// 1 if post-collision ones (gathered from x - c).
+// ---------------------------------------------------------------------------
+template <typename P>
+__device__ __forceinline__ void lds_node(const P *F, const P *G, int C, int x, int R, int shift,
+                                         P om, double omega, double n_rot, P (&fo)[7], P (&go)[7],
+                                         double &rho, double &T) {
+    P fv[7], gv[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        int s = x - (i - 3) * shift;
+        s = s < 0 ? 0 : (s >= R ? R - 1 : s);
+        fv[i] = F[i * C + s];
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j) gv[j] = G[j * C + x];
+    Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const double v = (double)fv[i], c = i - 3;
+        M.m0 += v;
+        M.m1[0] += c * v;
+        M.e2 += c * c * v;
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        if (j != 3) M.er += double((j - 3) * (j - 3)) * (double)gv[j];
+    double u[3] = {0.0, 0.0, 0.0}, Etot;
+    finish_moments<1>(M, n_rot, rho, u, T, Etot);
+
+    const P up[3] = {(P)u[0], P(0), P(0)};
+    const FeqCoef<P> fc = feq_coef<P, 1>((P)rho, up, (P)T);
+    P d[7];
+    static_for<0, 3>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        P fp, fm;
+        feq_pair<P, 1, i>(fc, fp, fm);
+        d[i] = om * (fp - fv[i]);
+        d[6 - i] = om * (fm - fv[6 - i]);
+    });
+    d[3] = om * (P(w_of<1>(3)) * fc.rho * fc.A0 - fv[3]);
+    if constexpr (sizeof(P) == 4) {
+        // conservative FP32 relaxation: defects to the rest and +-1 populations
+        P s0 = P(0), s1 = P(0), s2 = P(0);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            const P c = P(i - 3);
+            s0 += d[i];
+            s1 += c * d[i];
+            s2 += c * c * d[i];
+        }
+        const double t2 = omega * (M.m1[0] * M.m1[0] / rho + rho * T / (kR * kR) - M.e2);
+        const double R1[3] = {-(double)s1, 0.0, 0.0};
+        const Eps ep = eps_from_defects<1>(-(double)s0, R1, t2 - (double)s2);
+        d[3] += (P)ep.e[0];
+        d[2] += (P)ep.e[1];
+        d[4] += (P)ep.e[2];
+    }
+#pragma unroll
+    for (int i = 0; i < 7; ++i) fo[i] = fv[i] + d[i];
+
+    const GeqCoef<P> gc = geq_coef<P>((P)T);
+    const P nu = up[0] * P(1.0 / kR);
+    const int xm2 = x - 2 < 0 ? 0 : x - 2, xm1 = x - 1 < 0 ? 0 : x - 1;
+    const int xp1 = x + 1 >= R ? R - 1 : x + 1, xp2 = x + 2 >= R ? R - 1 : x + 2;
+    P adv[7], rl[7];
+    static_for<0, 7>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        adv[j] = upwind3<P>(nu, G[j * C + xm2], G[j * C + xm1], gv[j], G[j * C + xp1], G[j * C + xp2]);
+        rl[j] = om * (geq_dir<P, j>(gc) - gv[j]);
+    });
+    if constexpr (sizeof(P) == 4) {
+        double r0 = 0.0, r2 = 0.0, g0 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            r0 += (double)rl[j];
+            r2 += double((j - 3) * (j - 3)) * (double)rl[j];
+            g0 += (double)gv[j];
+        }
+        double al, ga;
+        gfix_from_defects(omega * (1.0 - g0) - r0, omega * (T / (kR * kR) - M.er) - r2, al, ga);
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            rl[j] += P(kW1[iabs(j - 3)]) * ((P)al + P((j - 3) * (j - 3)) * (P)ga);
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j) go[j] = gv[j] - adv[j] + rl[j];
+}
+
+// 0 healthy, 1 non-finite, 2 rho <= 0 or T <= 0.
+__device__ __forceinline__ int health(double rho, double T) {
+    if (!__builtin_isfinite(rho) || !__builtin_isfinite(T)) return 1;
+    return (rho <= 0.0 || T <= 0.0) ? 2 : 0;
+}
+
+// Advance the region [0, R) held in LDS buffer `cur` by `steps` steps,
+// ping-ponging between the two LDS buffers (one barrier per step).  `shift`
+// is the representation in `cur` on entry (0 streamed, 1 post-collision).
+// Nodes [vlo, vhi) are health-checked each step (their values are exact at
+// every step); on failure *bad is set and the loop stops.  Returns the
+// buffer index holding the result; *shift_out its representation.
+template <typename P, int B>
+__device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, double omega,
+                       double n_rot, int vlo, int vhi, int *bad, int *shift_out) {
+    int cur = 0;
+    for (int s = 0; s < steps; ++s) {
+        const P *Fi = F + cur * 7 * C, *Gi = G + cur * 7 * C;
+        P *Fo = F + (cur ^ 1) * 7 * C, *Go = G + (cur ^ 1) * 7 * C;
+        int h = 0;
+#pragma unroll 1
+        for (int x = threadIdx.x; x < R; x += B) {
+            P fo[7], go[7];
+            double rho, T;
+            lds_node<P>(Fi, Gi, C, x, R, shift, om, omega, n_rot, fo, go, rho, T);
+#pragma unroll
+            for (int i = 0; i < 7; ++i) Fo[i * C + x] = fo[i];
+#pragma unroll
+            for (int j = 0; j < 7; ++j) Go[j * C + x] = go[j];
+            if (x >= vlo && x < vhi) {
+                const int hh = health(rho, T);
+                h = hh > h ? hh : h;
+            }
+        }
+        if (h) atomicMax(bad, h);
+        shift = 1;
+        cur ^= 1;
+        __syncthreads();
+        if (*bad) break;
+    }
+    *shift_out = shift;
+    return cur;
+}
+
+template <typename P, int B>
+__global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int C = a.chunk;
+    P *F = reinterpret_cast<P *>(smem_raw);  // [2][7][C]
+    P *G = F + 14 * C;                        // [2][7][C]
+    __shared__ int s_item, s_bad;
+    const uint32_t tot = a.total;
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(a.counter, 1);
+            s_bad = 0;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item >= a.num) break;  // uniform: every workgroup reaches this exit
+        const int t = a.order[item];
+        const int64_t base = a.offsets[t];
+        const int L = (int)(a.offsets[t + 1] - base);
+        if (L < 1) {  // empty tube: nothing to advance
+            if (threadIdx.x == 0) a.status[t] = 3;
+            __syncthreads();
+            continue;
+        }
+        const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
+        const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
+        const P om = (P)omega;
+        const P *f0 = reinterpret_cast<const P *>(a.f[0]);
+        const P *g0 = reinterpret_cast<const P *>(a.g[0]);
+
+        if (L <= C) {
+            // whole tube on chip
+            for (int e = threadIdx.x; e < 7 * L; e += B) {
+                const int i = e / L, x = e - i * L;
+                F[i * C + x] = f0[(size_t)i * tot + base + x];
+                G[i * C + x] = g0[(size_t)i * tot + base + x];
+            }
+            __syncthreads();
+            int shift;
+            const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, &s_bad, &shift);
+            const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+            P *f0w = reinterpret_cast<P *>(a.f[0]);
+            P *g0w = reinterpret_cast<P *>(a.g[0]);
+            // back to streamed form: f(x) = f*(clamp(x - c))
+            for (int e = threadIdx.x; e < 7 * L; e += B) {
+                const int i = e / L, x = e - i * L;
+                int sx = x - (i - 3) * shift;
+                sx = sx < 0 ? 0 : (sx >= L ? L - 1 : sx);
+                f0w[(size_t)i * tot + base + x] = Fr[i * C + sx];
+                g0w[(size_t)i * tot + base + x] = Gr[i * C + x];
+            }
+        } else {
+            // passes of `superstep` steps over halo'd chunks; even pass count
+            const int S0 = a.superstep;
+            int passes = (int)((steps + S0 - 1) / S0);
+            if (passes < 2) passes = 2;
+            if (passes & 1) ++passes;
+            int64_t done = 0;
+            for (int p = 0; p < passes && !s_bad; ++p) {
+                const int sp = (int)((steps - done) / (passes - p));
+                const P *fs = reinterpret_cast<const P *>(a.f[p & 1]);
+                const P *gs = reinterpret_cast<const P *>(a.g[p & 1]);
+                P *fd = reinterpret_cast<P *>(a.f[(p + 1) & 1]);
+                P *gd = reinterpret_cast<P *>(a.g[(p + 1) & 1]);
+                const int halo = 3 * sp;
+                const int inner = C - 2 * halo;  // > 0 by the host's choice of superstep
+                for (int c0 = 0; c0 < L; c0 += inner) {
+                    const int c1 = c0 + inner < L ? c0 + inner : L;
+                    const int lo = c0 - halo > 0 ? c0 - halo : 0;
+                    const int hi = c1 + halo < L ? c1 + halo : L;
+                    const int R = hi - lo;
+                    for (int e = threadIdx.x; e < 7 * R; e += B) {
+                        const int i = e / R, x = e - i * R;
+                        F[i * C + x] = fs[(size_t)i * tot + base + lo + x];
+                        G[i * C + x] = gs[(size_t)i * tot + base + lo + x];
+                    }
+                    __syncthreads();
+                    int shift;
+                    const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo,
+                                                  &s_bad, &shift);
+                    const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+                    const int W = c1 - c0;
+                    for (int e = threadIdx.x; e < 7 * W; e += B) {
+                        const int i = e / W, x = (c0 - lo) + (e - i * W);
+                        int sx = x - (i - 3) * shift;
+                        sx = sx < 0 ? 0 : (sx >= R ? R - 1 : sx);
+                        fd[(size_t)i * tot + base + lo + x] = Fr[i * C + sx];
+                        gd[(size_t)i * tot + base + lo + x] = Gr[i * C + x];
+                    }
+                    __syncthreads();
+                }
+                done += sp;
+                __threadfence();
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x == 0) a.status[t] = s_bad;
+        __syncthreads();
+    }
+}
+
+}  // namespace lbmx
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace {
+
+lbm_status bfail(lbm_status s, const std::string &m) {
+    lbmx::set_error(m.c_str());
+    return s;
+}
+
+lbm_status bvalidate(const lbm_batch_desc *d) {
+    if (!d) return bfail(LBM_EINVAL, "batch descriptor is NULL");
+    if (d->abi_version != LBM_ABI_VERSION) return bfail(LBM_EINVAL, "abi_version mismatch");
+    if (d->dtype != LBM_F32 && d->dtype != LBM_F64) return bfail(LBM_EINVAL, "dtype must be F32 or F64");
+    if (d->num_instances < 1 || d->num_instances > (1 << 24))
+        return bfail(LBM_EINVAL, "num_instances must be in [1, 2^24]");
+    if (d->total_nodes < 4 * d->num_instances || d->total_nodes >= (1LL << 31))
+        return bfail(LBM_EINVAL, "total_nodes must be >= 4 * num_instances and < 2^31");
+    if (!d->offsets || !d->n_rot || !d->tau || !d->nsteps || !d->status || !d->workspace)
+        return bfail(LBM_EINVAL, "device arrays must not be NULL");
+    if (!d->f[0] || !d->f[1] || !d->g[0] || !d->g[1] || d->f[0] == d->f[1] || d->g[0] == d->g[1])
+        return bfail(LBM_EINVAL, "population buffers must be non-NULL and distinct");
+    if (d->block != 0 && d->block != 256 && d->block != 512 && d->block != 1024)
+        return bfail(LBM_EINVAL, "block must be 0, 256, 512 or 1024");
+    if (d->superstep < 0 || d->superstep > 128) return bfail(LBM_EINVAL, "superstep must be in [0, 128]");
+    return LBM_OK;
+}
+
+struct Launch {
+    int block, chunk, superstep;
+    size_t lds;
+};
+
+// Chunk capacity: the largest multiple of 64 nodes whose two LDS buffers of
+// 14 populations fit the LDS budget (at most `chunk` if given).
+lbm_status plan(const lbm_batch_desc *d, Launch *L) {
+    const int B = d->block ? d->block : (d->dtype == LBM_F32 ? 1024 : 512);
+    const size_t sz = d->dtype == LBM_F32 ? 4 : 8;
+    const size_t budget = 156 * 1024;
+    int C = (int)(budget / (28 * sz)) / 64 * 64;
+    if (d->chunk > 0) {
+        if (d->chunk < 64) return bfail(LBM_EINVAL, "chunk must be >= 64");
+        if (d->chunk / 64 * 64 < C) C = d->chunk / 64 * 64;
+    }
+    const int S = d->superstep ? d->superstep : (d->dtype == LBM_F32 ? 16 : 8);
+    if (C - 6 * S < 64) return bfail(LBM_EINVAL, "superstep too large for the chunk");
+    L->block = B;
+    L->chunk = C;
+    L->superstep = S;
+    L->lds = 28 * sz * (size_t)C;
+    return LBM_OK;
+}
+
+// prepare = true: raise the kernel's dynamic-LDS limit (outside capture);
+// prepare = false: launch.
+template <typename P, int B> hipError_t launch_batch_t(const lbmx::BatchArgs &a, size_t lds, int grid,
+                                                       hipStream_t s, bool prepare) {
+    auto kern = lbmx::k_batch<P, B>;
+    if (prepare)
+        return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(B), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename P> hipError_t launch_batch_p(const Launch &L, const lbmx::BatchArgs &a, int grid,
+                                                hipStream_t s, bool prepare) {
+    if (L.block == 256) return launch_batch_t<P, 256>(a, L.lds, grid, s, prepare);
+    if (L.block == 512) return launch_batch_t<P, 512>(a, L.lds, grid, s, prepare);
+    if (L.block == 1024) return launch_batch_t<P, 1024>(a, L.lds, grid, s, prepare);
+    return hipErrorInvalidValue;
+}
+
+struct GraphEntry {
+    lbm_batch_desc d;
+    hipGraphExec_t exec;
+};
+std::mutex g_mu;
+std::vector<GraphEntry> g_cache;
+
+bool same_desc(const lbm_batch_desc &x, const lbm_batch_desc &y) {
+    return x.dtype == y.dtype && x.num_instances == y.num_instances &&
+           x.total_nodes == y.total_nodes && x.offsets == y.offsets && x.n_rot == y.n_rot &&
+           x.tau == y.tau && x.nsteps == y.nsteps && x.f[0] == y.f[0] && x.f[1] == y.f[1] &&
+           x.g[0] == y.g[0] && x.g[1] == y.g[1] && x.status == y.status &&
+           x.workspace == y.workspace && x.block == y.block && x.chunk == y.chunk &&
+           x.superstep == y.superstep;
+}
+
+hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s, bool prepare) {
+    lbmx::BatchArgs a;
+    a.offsets = d->offsets;
+    a.n_rot = d->n_rot;
+    a.tau = d->tau;
+    a.nsteps = d->nsteps;
+    for (int k = 0; k < 2; ++k) {
+        a.f[k] = d->f[k];
+        a.g[k] = d->g[k];
+    }
+    a.status = d->status;
+    a.counter = reinterpret_cast<int32_t *>(d->workspace);
+    a.order = a.counter + 64;
+    a.num = (int)d->num_instances;
+    a.total = (uint32_t)d->total_nodes;
+    a.chunk = L.chunk;
+    a.superstep = L.superstep;
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int grid = (int)(d->num_instances < cus ? d->num_instances : cus);
+    if (!prepare) {
+        hipLaunchKernelGGL(lbmx::k_batch_order, dim3(1), dim3(1024), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return d->dtype == LBM_F32 ? launch_batch_p<float>(L, a, grid, s, prepare)
+                               : launch_batch_p<double>(L, a, grid, s, prepare);
+}
+
+}  // namespace
 
 extern "C" {
-size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc) { (void)desc; return 0; }
-lbm_status lbm_batch_init(const lbm_batch_desc *, const double *, const double *, const double *,
-                          void *) { return LBM_EUNSUPPORTED; }
-lbm_status lbm_batch_step(const lbm_batch_desc *, void *) { return LBM_EUNSUPPORTED; }
-lbm_status lbm_batch_moments(const lbm_batch_desc *, double *, double *, double *, void *) {
-    return LBM_EUNSUPPORTED;
+
+size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc) {
+    if (!desc || desc->num_instances < 1) return 0;
+    return ((64 * 4 + (size_t)desc->num_instances * 4 + 255) / 256) * 256;
 }
+
+lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const double *u,
+                          const double *T, void *hip_stream) {
+    lbm_status st = bvalidate(desc);
+    if (st) return st;
+    if (!rho || !u || !T) return bfail(LBM_EINVAL, "rho, u, T must not be NULL");
+    lbmx::InitArgs a{rho, u, T, desc->f[0], desc->g[0], (uint32_t)desc->total_nodes};
+    hipError_t e = lbmx::launch_init(desc->dtype, 1, a, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("batch init: ") + hipGetErrorString(e));
+    return LBM_OK;
 }
+
+lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream) {
+    lbm_status st = bvalidate(desc);
+    if (st) return st;
+    Launch L;
+    st = plan(desc, &L);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &en : g_cache)
+        if (same_desc(en.d, *desc)) {
+            hipError_t e = hipGraphLaunch(en.exec, s);
+            if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
+            return LBM_OK;
+        }
+    // record the order + persistent kernels once on a private stream
+    hipError_t ep = enqueue_batch(desc, L, s, true);
+    if (ep != hipSuccess) return bfail(LBM_ELAUNCH, std::string("batch LDS limit: ") + hipGetErrorString(ep));
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return bfail(LBM_EDEVICE, "stream create failed");
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = enqueue_batch(desc, L, cap, false);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    hipStreamDestroy(cap);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return bfail(LBM_ELAUNCH, std::string("batch capture: ") +
+                                      hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if (g_cache.size() >= 16) {
+        hipGraphExecDestroy(g_cache.front().exec);
+        g_cache.erase(g_cache.begin());
+    }
+    g_cache.push_back({*desc, exec});
+    e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_moments(const lbm_batch_desc *desc, double *rho, double *u, double *T,
+                             void *hip_stream) {
+    lbm_status st = bvalidate(desc);
+    if (st) return st;
+    if (!rho && !u && !T) return LBM_OK;
+    lbmx::FieldArgs a = {};
+    a.f = desc->f[0];
+    a.g = desc->g[0];
+    a.n0 = (int)desc->total_nodes;
+    a.n1 = 1;
+    a.n2 = 1;
+    a.N = (uint32_t)desc->total_nodes;
+    a.streamed = 1;  // the batch state is kept streamed
+    a.n_rot = 0.0;
+    a.rho = rho;
+    a.u = u;
+    a.T = T;
+    a.offsets = desc->offsets;  // per-node n from the node's tube
+    a.n_rot_inst = desc->n_rot;
+    a.num_inst = (int)desc->num_instances;
+    int nb = 0;
+    hipError_t e = lbmx::launch_fields(desc->dtype, 1, a, &nb, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("batch moments: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // extern "C"

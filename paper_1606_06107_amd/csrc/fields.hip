@@ -83,8 +83,18 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_fields(Fie
         M.e2 += c2_of<D>(i) * v;
     }
     for (int j = 0; j < 7; ++j) M.er += double((j - 3) * (j - 3)) * (double)pop<P>(a.g, j, a.N)[xn];
+    double n_rot = a.n_rot;
+    if (a.offsets) {  // packed batch: binary search for the node's tube
+        int lo = 0, hi = a.num_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.offsets[mid] <= (int64_t)xn) lo = mid;
+            else hi = mid - 1;
+        }
+        n_rot = a.n_rot_inst[lo];
+    }
     double rho, u[3] = {0.0, 0.0, 0.0}, T, Etot;
-    finish_moments<D>(M, a.n_rot, rho, u, T, Etot);
+    finish_moments<D>(M, n_rot, rho, u, T, Etot);
     if (valid) {
         if (a.rho) a.rho[x] = rho;
         if (a.T) a.T[x] = T;

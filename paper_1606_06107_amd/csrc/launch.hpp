@@ -34,6 +34,11 @@ struct FieldArgs {
     double *rho, *u, *T;  // any may be NULL
     double *partials;     // NULL or [nblocks][2+D]
     void *f_out, *g_out;  // export targets (may be NULL)
+    // Packed batches: node x belongs to tube t with offsets[t] <= x <
+    // offsets[t+1] and uses n = n_rot_inst[t] instead of n_rot.
+    const int64_t *offsets;
+    const double *n_rot_inst;
+    int num_inst;
 };
 
 struct InitArgs {
@@ -43,6 +48,8 @@ struct InitArgs {
 };
 
 hipError_t launch_init(int dtype, int dim, const InitArgs &a, hipStream_t s);
+// Message returned by lbm_last_error() on this thread.
+void set_error(const char *msg);
 // tile = {tx, ty, tz}; returns hipErrorInvalidValue for a shape not compiled.
 hipError_t launch_step(int dtype, int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_12_f32(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
