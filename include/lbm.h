@@ -169,7 +169,10 @@ typedef struct {
     void *f[2];             /* device [7][total] of dtype: f[0] holds the state,
                                f[1] is scratch */
     void *g[2];             /* device [7][total] of dtype: same roles */
-    int32_t *status;        /* device [I] out: 0 ok, 1 non-finite, 2 rho<=0 or T<=0 */
+    int32_t *status;        /* device [I] out: 0 ok, 1 non-finite, 2 rho<=0 or T<=0,
+                               3 empty tube; a failing tube stops at the step
+                               that failed and its state is then unspecified */
+    int64_t *steps_done;    /* device [I] out (may be NULL): steps completed */
     void *workspace;        /* device, lbm_batch_workspace_bytes() bytes */
     int32_t block;          /* threads per workgroup: 256, 512 or 1024 (0 = default) */
     int32_t chunk;          /* nodes per on-chip chunk, 0 = largest that fits */
@@ -195,6 +198,95 @@ lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream);
  * any may be NULL. */
 lbm_status lbm_batch_moments(const lbm_batch_desc *desc, double *rho, double *u, double *T,
                              void *hip_stream);
+
+
+/* ------------------------------------------------------------------------ */
+/* Learned surrogate of the batched tubes: a 1-D neural operator that maps   */
+/* (rho, u, T, gamma) of a tube to (rho, u, T) k = 16 lattice steps later.   */
+/* The plain scheme above generates its training data, judges its error and  */
+/* replaces it wherever a conservation/admissibility check fails.  The paper */
+/* has no learned component; only the fallback and the judge are its method. */
+/*                                                                          */
+/* Network (tokens = patches of 4 nodes, C = 64 channels, 4 blocks):         */
+/*   X  [M][16]  features (rho-0.5)/0.5, u/0.5, (T-1)/0.5, (gamma-1.4)/0.3   */
+/*               of the 4 nodes of a patch, feature p*4 + c                  */
+/*   H0 = X We^T + be                                       We [64][16]      */
+/*   block b: Hc = H + bc + dwconv5(H)   (per channel, zero padding, taps    */
+/*                                       kc[64][5] at token offsets -2..2)   */
+/*            H' = Hc + W2 gelu(W1 Hc + b1) + b2    W1 [128][64], W2 [64][128] */
+/*   Y  = H4 Wh^T + bh                                      Wh [12][64]      */
+/*   out_c(node 4t+p) = in_c(node 4t+p) + 0.1 * Y[t][p*3 + c]               */
+/* gelu(z) = z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))).                  */
+/* Matrix products take BF16 operands (weights and activations rounded to    */
+/* nearest-even) on MFMA with FP32 accumulation; everything else is FP32.    */
+/* Parameter vector (FP32, this order, LBM_SUR_NPARAMS = 69708 values):      */
+/*   We, be, {kc, bc, W1, b1, W2, b2} x 4 blocks, Wh, bh  (row-major)        */
+/* ------------------------------------------------------------------------ */
+#define LBM_SUR_NPARAMS 69708
+#define LBM_SUR_K 16 /* lattice steps per surrogate call */
+
+typedef struct {
+    int32_t abi_version;
+    int32_t batch;        /* B tubes */
+    int32_t length;       /* L nodes per tube, a multiple of 128 */
+    const float *params;  /* device [LBM_SUR_NPARAMS] FP32 master parameters */
+    void *params_bf16;    /* device, lbm_sur_bf16_bytes(): BF16 copies of the
+                             weight matrices and their transposes, written by
+                             lbm_sur_pack / lbm_sur_adam */
+    void *workspace;      /* device, lbm_sur_workspace_bytes() bytes */
+} lbm_sur_desc;
+
+size_t lbm_sur_bf16_bytes(void);
+size_t lbm_sur_workspace_bytes(const lbm_sur_desc *desc);
+
+/* Refresh params_bf16 from params (after initialising or loading them). */
+lbm_status lbm_sur_pack(const lbm_sur_desc *desc, void *hip_stream);
+
+/* Inference: x [3][B][L] FP64 fields (rho, u, T), gamma [B] FP64 ->
+ * y [3][B][L] FP64 predicted fields LBM_SUR_K steps later.  y may not
+ * alias x. */
+lbm_status lbm_sur_forward(const lbm_sur_desc *desc, const double *x, const double *gamma,
+                           double *y, void *hip_stream);
+
+/* Training step: forward on x, loss = mean over nodes and channels of
+ * (Y_c - (target_c - x_c) / 0.1)^2, backward.  grads [LBM_SUR_NPARAMS] FP32
+ * are overwritten; loss [1] FP32 (device). */
+lbm_status lbm_sur_backward(const lbm_sur_desc *desc, const double *x, const double *gamma,
+                            const double *target, float *grads, float *loss, void *hip_stream);
+
+/* Adam on the FP32 master parameters (m, v: FP32 moments of the same size),
+ * step >= 1, then refresh params_bf16.  Decoupled from the loss scale. */
+lbm_status lbm_sur_adam(const lbm_sur_desc *desc, float *params, float *m, float *v,
+                        const float *grads, float lr, float beta1, float beta2, float eps,
+                        int64_t step, void *hip_stream);
+
+/* Admission check of a surrogate step for every tube b: with n_b from
+ * gamma_b (n = 2/(gamma-1) - 1), the totals mass = sum rho, momentum =
+ * sum rho u and energy = sum rho (u^2/2 + (1+n) T/2) of y must match those
+ * of x within tol_mass, tol_mom (relative to mass * sqrt(max T)) and
+ * tol_energy (relative), and y must be finite with rho > 0 and T > 0.
+ * accept[b] = 1 or 0 (device int32).  The totals use FP64 and a fixed
+ * reduction order. */
+lbm_status lbm_sur_check(const lbm_sur_desc *desc, const double *x, const double *y,
+                         const double *gamma, double tol_mass, double tol_mom, double tol_energy,
+                         int32_t *accept, void *hip_stream);
+
+/* Fallback preparation: for every tube b with accept[b] == 0 and
+ * valid[b] == 0 write the equilibrium populations of x (f = f^eq, g = g^eq,
+ * Sec. IV) into the packed FP32 batch buffers f0 [7][B*L], g0 [7][B*L] at
+ * the tube's slot.  valid[b] != 0 means those buffers already hold the
+ * tube's populations at the time of x (its previous chunk ran the plain
+ * scheme), so the non-equilibrium part is kept.  nsteps[b] = LBM_SUR_K for
+ * rejected tubes, 0 for accepted ones. */
+lbm_status lbm_sur_lift(const lbm_sur_desc *desc, const double *x, const int32_t *accept,
+                        const int32_t *valid, void *f0, void *g0, int64_t *nsteps,
+                        void *hip_stream);
+
+/* out[c][b][l] = accept[b] ? y : z (FP64 [3][B][L]); out may alias y or z.
+ * valid[b] = accept[b] ? 0 : 1 (the batch buffers hold tube b's populations
+ * at the new time exactly when it ran the plain scheme). */
+lbm_status lbm_sur_merge(const lbm_sur_desc *desc, const int32_t *accept, const double *y,
+                         const double *z, double *out, int32_t *valid, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,7 @@ first use does, and fails loudly if it has not been built.
 """
 from ._lib import LbmError, load  # noqa: F401
 
-__all__ = ["LbmError", "load", "Sim", "Batch", "lattice_info"]
+__all__ = ["LbmError", "load", "Sim", "Batch", "Surrogate", "lattice_info"]
 
 
 def __getattr__(name):
@@ -19,4 +19,7 @@ def __getattr__(name):
     if name == "Batch":
         from . import batch
         return batch.Batch
+    if name == "Surrogate":
+        from . import surrogate
+        return surrogate.Surrogate
     raise AttributeError(name)

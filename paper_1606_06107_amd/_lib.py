@@ -30,8 +30,17 @@ class LbmBatchDesc(ctypes.Structure):
     _fields_ = [("abi_version", c_i32), ("dtype", c_i32), ("num_instances", c_i64),
                 ("total_nodes", c_i64), ("offsets", c_vp), ("n_rot", c_vp), ("tau", c_vp),
                 ("nsteps", c_vp), ("f", c_vp * 2), ("g", c_vp * 2), ("status", c_vp),
+                ("steps_done", c_vp),
                 ("workspace", c_vp), ("block", c_i32), ("chunk", c_i32), ("superstep", c_i32)]
 
+
+class LbmSurDesc(ctypes.Structure):
+    _fields_ = [("abi_version", c_i32), ("batch", c_i32), ("length", c_i32), ("params", c_vp),
+                ("params_bf16", c_vp), ("workspace", c_vp)]
+
+
+LBM_SUR_NPARAMS = 69708
+LBM_SUR_K = 16
 
 # name -> (restype, argtypes); every symbol include/lbm.h declares
 SIGNATURES = {
@@ -52,6 +61,17 @@ SIGNATURES = {
     "lbm_batch_init": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp, c_vp, c_vp, c_vp]),
     "lbm_batch_step": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp]),
     "lbm_batch_moments": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp, c_vp, c_vp, c_vp]),
+    "lbm_sur_bf16_bytes": (c_sz, []),
+    "lbm_sur_workspace_bytes": (c_sz, [ctypes.POINTER(LbmSurDesc)]),
+    "lbm_sur_pack": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp]),
+    "lbm_sur_forward": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp]),
+    "lbm_sur_backward": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lbm_sur_adam": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, ctypes.c_float,
+                             ctypes.c_float, ctypes.c_float, ctypes.c_float, c_i64, c_vp]),
+    "lbm_sur_check": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_dbl, c_dbl, c_dbl,
+                              c_vp, c_vp]),
+    "lbm_sur_lift": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lbm_sur_merge": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
 }
 
 _lib = None

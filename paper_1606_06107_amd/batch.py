@@ -38,6 +38,7 @@ class Batch:
         self.f = [torch.empty((7, self.total), dtype=dtype, device=dev) for _ in range(2)]
         self.g = [torch.empty((7, self.total), dtype=dtype, device=dev) for _ in range(2)]
         self.status = torch.full((self.I,), -1, dtype=torch.int32, device=dev)
+        self.steps_done = torch.zeros((self.I,), dtype=torch.int64, device=dev)
         d = L.LbmBatchDesc()
         d.abi_version = L.LBM_ABI_VERSION
         d.dtype = L.LBM_F32 if dtype == torch.float32 else L.LBM_F64
@@ -51,6 +52,7 @@ class Batch:
             d.f[k] = self.f[k].data_ptr()
             d.g[k] = self.g[k].data_ptr()
         d.status = self.status.data_ptr()
+        d.steps_done = self.steps_done.data_ptr()
         d.block, d.chunk, d.superstep = int(block), int(chunk), int(superstep)
         nbytes = self.lib.lbm_batch_workspace_bytes(ctypes.byref(d))
         self.workspace = torch.empty(max(nbytes, 256) // 4 + 64, dtype=torch.int32, device=dev)

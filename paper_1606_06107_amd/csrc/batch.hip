@@ -38,6 +38,7 @@ struct BatchArgs {
     const int64_t *nsteps;
     void *f[2], *g[2];  // packed [7][total]
     int32_t *status;
+    int64_t *steps_done;  // may be NULL
     int32_t *order;     // workspace: processing order
     int32_t *counter;   // workspace: queue head
     int num;
@@ -199,8 +200,9 @@ __device__ __forceinline__ int health(double rho, double T) {
 // buffer index holding the result; *shift_out its representation.
 template <typename P, int B>
 __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, double omega,
-                       double n_rot, int vlo, int vhi, int *bad, int *shift_out) {
+                       double n_rot, int vlo, int vhi, int *bad, int *shift_out, int *ran) {
     int cur = 0;
+    *ran = 0;
     for (int s = 0; s < steps; ++s) {
         const P *Fi = F + cur * 7 * C, *Gi = G + cur * 7 * C;
         P *Fo = F + (cur ^ 1) * 7 * C, *Go = G + (cur ^ 1) * 7 * C;
@@ -222,6 +224,7 @@ __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, dou
         if (h) atomicMax(bad, h);
         shift = 1;
         cur ^= 1;
+        *ran = s + 1;
         __syncthreads();
         if (*bad) break;
     }
@@ -250,13 +253,17 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
         const int64_t base = a.offsets[t];
         const int L = (int)(a.offsets[t + 1] - base);
         if (L < 1) {  // empty tube: nothing to advance
-            if (threadIdx.x == 0) a.status[t] = 3;
+            if (threadIdx.x == 0) {
+                a.status[t] = 3;
+                if (a.steps_done) a.steps_done[t] = 0;
+            }
             __syncthreads();
             continue;
         }
         const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
         const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
         const P om = (P)omega;
+        int64_t done_total = 0;
         const P *f0 = reinterpret_cast<const P *>(a.f[0]);
         const P *g0 = reinterpret_cast<const P *>(a.g[0]);
 
@@ -268,8 +275,10 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                 G[i * C + x] = g0[(size_t)i * tot + base + x];
             }
             __syncthreads();
-            int shift;
-            const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, &s_bad, &shift);
+            int shift, ran;
+            const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, &s_bad, &shift,
+                                          &ran);
+            done_total = ran;
             const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
             P *f0w = reinterpret_cast<P *>(a.f[0]);
             P *g0w = reinterpret_cast<P *>(a.g[0]);
@@ -296,6 +305,7 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                 P *gd = reinterpret_cast<P *>(a.g[(p + 1) & 1]);
                 const int halo = 3 * sp;
                 const int inner = C - 2 * halo;  // > 0 by the host's choice of superstep
+                int pass_ran = sp;
                 for (int c0 = 0; c0 < L; c0 += inner) {
                     const int c1 = c0 + inner < L ? c0 + inner : L;
                     const int lo = c0 - halo > 0 ? c0 - halo : 0;
@@ -307,9 +317,10 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                         G[i * C + x] = gs[(size_t)i * tot + base + lo + x];
                     }
                     __syncthreads();
-                    int shift;
+                    int shift, ran;
                     const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo,
-                                                  &s_bad, &shift);
+                                                  &s_bad, &shift, &ran);
+                    pass_ran = ran < pass_ran ? ran : pass_ran;
                     const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
                     const int W = c1 - c0;
                     for (int e = threadIdx.x; e < 7 * W; e += B) {
@@ -321,12 +332,16 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                     }
                     __syncthreads();
                 }
+                done_total = done + pass_ran;
                 done += sp;
                 __threadfence();
                 __syncthreads();
             }
         }
-        if (threadIdx.x == 0) a.status[t] = s_bad;
+        if (threadIdx.x == 0) {
+            a.status[t] = s_bad;
+            if (a.steps_done) a.steps_done[t] = done_total;
+        }
         __syncthreads();
     }
 }
@@ -418,7 +433,7 @@ bool same_desc(const lbm_batch_desc &x, const lbm_batch_desc &y) {
            x.total_nodes == y.total_nodes && x.offsets == y.offsets && x.n_rot == y.n_rot &&
            x.tau == y.tau && x.nsteps == y.nsteps && x.f[0] == y.f[0] && x.f[1] == y.f[1] &&
            x.g[0] == y.g[0] && x.g[1] == y.g[1] && x.status == y.status &&
-           x.workspace == y.workspace && x.block == y.block && x.chunk == y.chunk &&
+           x.workspace == y.workspace && x.steps_done == y.steps_done && x.block == y.block && x.chunk == y.chunk &&
            x.superstep == y.superstep;
 }
 
@@ -433,6 +448,7 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
         a.g[k] = d->g[k];
     }
     a.status = d->status;
+    a.steps_done = d->steps_done;
     a.counter = reinterpret_cast<int32_t *>(d->workspace);
     a.order = a.counter + 64;
     a.num = (int)d->num_instances;

@@ -1,0 +1,730 @@
+// Learned surrogate of the batched shock tubes (C ABI in include/lbm.h):
+// BF16-MFMA forward/backward kernels with FP32 accumulation, Adam, and the
+// admission check / equilibrium lift / merge used for the plain-scheme
+// fallback.
+//
+// Matrix products use v_mfma_f32_32x32x16_bf16 (gfx950).  Operand layout
+// (lane l of a wave): A fragment = 8 BF16 of row (l & 31), k = 8 (l >> 5) ..
+// +7; B fragment = 8 BF16 of column (l & 31) at the same k; the 16 FP32
+// results of lane l sit at column (l & 31), rows 8 (i >> 2) + 4 (l >> 5) +
+// (i & 3) for i = 0..15.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+
+#include "launch.hpp"
+#include "lbm.h"
+#include "lbm_device.hpp"
+
+namespace lbmx {
+namespace sur {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int C = 64, HID = 128, NB = 4, TAPS = 5, FIN = 16, FOUT = 12;
+constexpr int PATCH = 4;
+constexpr double OUT_SCALE = 0.1;
+// Feature normalisation (rho, u, T, gamma): (v - mu) / sd.
+__device__ constexpr double kMu[4] = {0.5, 0.0, 1.0, 1.4};
+__device__ constexpr double kSd[4] = {0.5, 0.5, 0.5, 0.3};
+
+// FP32 parameter offsets
+constexpr int P_WE = 0, P_BE = 1024, P_BLK = 1088, BLK = 16960;
+constexpr int B_KC = 0, B_BC = 320, B_W1 = 384, B_B1 = 8576, B_W2 = 8704, B_B2 = 16896;
+constexpr int P_WH = P_BLK + NB * BLK, P_BH = P_WH + FOUT * C, NPARAMS = P_BH + FOUT;
+static_assert(NPARAMS == LBM_SUR_NPARAMS, "parameter count");
+// BF16 copies (element offsets)
+constexpr int Q_WE = 0, Q_BLK = 1024, QBLK = 32768;  // per block: W1, W1t, W2, W2t
+constexpr int Q_W1 = 0, Q_W1T = 8192, Q_W2 = 16384, Q_W2T = 24576;
+constexpr int Q_WHP = Q_BLK + NB * QBLK;   // [32][64], rows >= 12 zero
+constexpr int Q_WHTP = Q_WHP + 32 * C;     // [64][16], cols >= 12 zero
+constexpr int QTOTAL = Q_WHTP + C * 16;
+
+// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
+__device__ __forceinline__ __bf16 to_bf16(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    uint16_t h;
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) h = (uint16_t)((u >> 16) | 0x40);
+    else h = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(__bf16, h);
+}
+__device__ __forceinline__ float from_bf16(__bf16 b) {
+    return __builtin_bit_cast(float, ((uint32_t)__builtin_bit_cast(uint16_t, b)) << 16);
+}
+
+__device__ __forceinline__ float gelu(float z) {
+    const float k = 0.7978845608028654f;  // sqrt(2/pi)
+    return 0.5f * z * (1.0f + tanhf(k * (z + 0.044715f * z * z * z)));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float k = 0.7978845608028654f;
+    const float t = tanhf(k * (z + 0.044715f * z * z * z));
+    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * k * (1.0f + 3.0f * 0.044715f * z * z);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[M][N] = A[M][K] Bt[N][K]^T (+ epilogue), A FP32 (rounded to BF16 on
+// load) or BF16, Bt BF16.  Workgroup = 4 waves = 128 rows x all N columns;
+// K is staged in LDS at once (rows padded by 8 elements).
+// ---------------------------------------------------------------------------
+enum { EPI_BIAS = 1, EPI_GELU = 2, EPI_RES = 4, EPI_F32 = 8, EPI_BF16 = 16 };
+
+struct GemmArgs {
+    int M, nvalid;
+    const void *A;
+    const __bf16 *Bt;
+    const float *bias;   // [nvalid]
+    const float *R;      // residual [M][N] FP32
+    float *out;          // [M][N] FP32
+    __bf16 *out_bf;      // [M][N] BF16
+    float *pre;          // [M][N] FP32 pre-activation (GELU)
+};
+
+template <int N, int K, bool AF32, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+    constexpr int KP = K + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 As[128 * KP];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[N * KP];
+    const int row0 = blockIdx.x * 128;
+    for (int e = threadIdx.x; e < 128 * (K / 8); e += 256) {
+        const int r = e / (K / 8), k8 = (e % (K / 8)) * 8;
+        const int gr = row0 + r;
+        bf16x8 v;
+        if (gr < g.M) {
+            if constexpr (AF32) {
+                const float *a = reinterpret_cast<const float *>(g.A) + (size_t)gr * K + k8;
+                const float4 p = *reinterpret_cast<const float4 *>(a);
+                const float4 q = *reinterpret_cast<const float4 *>(a + 4);
+                v[0] = to_bf16(p.x); v[1] = to_bf16(p.y); v[2] = to_bf16(p.z); v[3] = to_bf16(p.w);
+                v[4] = to_bf16(q.x); v[5] = to_bf16(q.y); v[6] = to_bf16(q.z); v[7] = to_bf16(q.w);
+            } else {
+                v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(g.A) +
+                                                      (size_t)gr * K + k8);
+            }
+        } else {
+            for (int j = 0; j < 8; ++j) v[j] = to_bf16(0.0f);
+        }
+        *reinterpret_cast<bf16x8 *>(&As[r * KP + k8]) = v;
+    }
+    for (int e = threadIdx.x; e < N * (K / 8); e += 256) {
+        const int n = e / (K / 8), k8 = (e % (K / 8)) * 8;
+        *reinterpret_cast<bf16x8 *>(&Bs[n * KP + k8]) =
+            *reinterpret_cast<const bf16x8 *>(g.Bt + (size_t)n * K + k8);
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    f32x16 acc[N / 32];
+#pragma unroll
+    for (int t = 0; t < N / 32; ++t)
+        for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < K; kk += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[(w * 32 + (l & 31)) * KP + kk + (l >> 5) * 8]);
+#pragma unroll
+        for (int t = 0; t < N / 32; ++t) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[(t * 32 + (l & 31)) * KP + kk + (l >> 5) * 8]);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < N / 32; ++t) {
+        const int col = t * 32 + (l & 31);
+        const float bias = ((EPI & EPI_BIAS) && col < g.nvalid) ? g.bias[col] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = row0 + w * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
+            if (row >= g.M) continue;
+            const size_t o = (size_t)row * N + col;
+            float v = acc[t][i] + bias;
+            if constexpr (EPI & EPI_GELU) {
+                g.pre[o] = v;
+                v = gelu(v);
+            }
+            if constexpr (EPI & EPI_RES) v += g.R[o];
+            if constexpr (EPI & EPI_F32) g.out[o] = v;
+            if constexpr (EPI & EPI_BF16) g.out_bf[o] = to_bf16(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: G[n][k] = sum_m A[m][n] B[m][k] over a 128-row chunk per
+// workgroup (partials [chunk][Nv][Kv]); optional bias gradient partial
+// sum_m A[m][n] ([chunk][Nv]).  A, B FP32 (rounded to BF16) or BF16 with row
+// lengths NA, KB; N, K are the padded MFMA sizes (multiples of 32).
+// ---------------------------------------------------------------------------
+struct WgArgs {
+    int M, Nv, Kv;
+    const void *A;
+    const void *B;
+    float *part;   // [gridDim.x][Nv][Kv]
+    float *bpart;  // [gridDim.x][Nv] or NULL
+};
+
+template <int N, int K, int NA, int KB, bool AF32, bool BF32>
+__global__ void __launch_bounds__(256) k_wgrad(WgArgs g) {
+    constexpr int MP = 128 + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 At[N * MP];
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[K * MP];
+    const int m0 = blockIdx.x * 128;
+    for (int e = threadIdx.x; e < N * 128; e += 256) {
+        const int m = e & 127, n = e >> 7;
+        __bf16 v = to_bf16(0.0f);
+        if (n < NA && m0 + m < g.M) {
+            if constexpr (AF32) v = to_bf16(reinterpret_cast<const float *>(g.A)[(size_t)(m0 + m) * NA + n]);
+            else v = reinterpret_cast<const __bf16 *>(g.A)[(size_t)(m0 + m) * NA + n];
+        }
+        At[n * MP + m] = v;
+    }
+    for (int e = threadIdx.x; e < K * 128; e += 256) {
+        const int m = e & 127, k = e >> 7;
+        __bf16 v = to_bf16(0.0f);
+        if (k < KB && m0 + m < g.M) {
+            if constexpr (BF32) v = to_bf16(reinterpret_cast<const float *>(g.B)[(size_t)(m0 + m) * KB + k]);
+            else v = reinterpret_cast<const __bf16 *>(g.B)[(size_t)(m0 + m) * KB + k];
+        }
+        Bt[k * MP + m] = v;
+    }
+    __syncthreads();
+    if (g.bpart) {
+        for (int n = threadIdx.x; n < g.Nv; n += 256) {
+            float s = 0.0f;
+            for (int m = 0; m < 128; ++m) s += from_bf16(At[n * MP + m]);
+            g.bpart[(size_t)blockIdx.x * g.Nv + n] = s;
+        }
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    constexpr int TN = N / 32, TK = K / 32, TT = TN * TK;
+    for (int t = w; t < TT; t += 4) {
+        const int tn = t / TK, tk = t % TK;
+        f32x16 acc;
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+#pragma unroll
+        for (int mm = 0; mm < 128; mm += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&At[(tn * 32 + (l & 31)) * MP + mm + (l >> 5) * 8]);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bt[(tk * 32 + (l & 31)) * MP + mm + (l >> 5) * 8]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        const int k = tk * 32 + (l & 31);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int n = tn * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
+            if (n < g.Nv && k < g.Kv) g.part[((size_t)blockIdx.x * g.Nv + n) * g.Kv + k] = acc[i];
+        }
+    }
+}
+
+// out[j] (= or +=) sum_c part[c][j], c in order.
+__global__ void __launch_bounds__(256) k_reduce_parts(const float *part, int nch, int len, float *out,
+                                                      int accumulate) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= len) return;
+    float s = 0.0f;
+    for (int c = 0; c < nch; ++c) s += part[(size_t)c * len + j];
+    out[j] = accumulate ? out[j] + s : s;
+}
+
+// ---------------------------------------------------------------------------
+// Tokens, convolution, head output, loss, GELU backward
+// ---------------------------------------------------------------------------
+struct Shape {
+    int B, L, T, M;  // tubes, nodes per tube, tokens per tube, tokens
+};
+
+// X[b*T + t][p*4 + c] = bf16((field_c(b, 4t+p) - mu_c) / sd_c); c = 3 is gamma_b.
+__global__ void __launch_bounds__(256) k_patchify(Shape s, const double *x, const double *gamma,
+                                                  __bf16 *X) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= s.M * FIN) return;
+    const int tok = e / FIN, f = e % FIN, p = f / 4, c = f % 4;
+    const int b = tok / s.T, t = tok % s.T;
+    const size_t node = (size_t)b * s.L + t * PATCH + p;
+    const double v = c < 3 ? x[(size_t)c * s.B * s.L + node] : gamma[b];
+    X[e] = to_bf16((float)((v - kMu[c]) / kSd[c]));
+}
+
+// Hc = H + bc + sum_k kc[c][k] H[t+k-2] (zero padding at tube ends).
+__global__ void __launch_bounds__(256) k_conv_fwd(Shape s, const float *H, const float *kc,
+                                                  const float *bc, float *Hc) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= s.M * C) return;
+    const int tok = e / C, c = e % C, t = tok % s.T;
+    float v = H[e] + bc[c];
+#pragma unroll
+    for (int k = 0; k < TAPS; ++k) {
+        const int tt = t + k - 2;
+        if (tt >= 0 && tt < s.T) v += kc[c * TAPS + k] * H[(size_t)(tok + k - 2) * C + c];
+    }
+    Hc[e] = v;
+}
+
+// dH = dHc + sum_k kc[c][k] dHc[t-k+2]; partials of dkc and dbc per 64-row
+// workgroup: part[wg][c][0..4] taps, [5] bias.
+__global__ void __launch_bounds__(256) k_conv_bwd(Shape s, const float *dHc, const float *H,
+                                                  const float *kc, float *dH, float *part) {
+    __shared__ float red[4][C][6];
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 64 + q * 16;
+    float acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int r = r0; r < r0 + 16 && r < s.M; ++r) {
+        const int t = r % s.T;
+        const float d = dHc[(size_t)r * C + c];
+        float v = d;
+#pragma unroll
+        for (int k = 0; k < TAPS; ++k) {
+            const int tt = t - k + 2;
+            if (tt >= 0 && tt < s.T) v += kc[c * TAPS + k] * dHc[(size_t)(r - k + 2) * C + c];
+            const int th = t + k - 2;
+            if (th >= 0 && th < s.T) acc[k] += d * H[(size_t)(r + k - 2) * C + c];
+        }
+        acc[5] += d;
+        dH[(size_t)r * C + c] = v;
+    }
+    for (int k = 0; k < 6; ++k) red[q][c][k] = acc[k];
+    __syncthreads();
+    if (q == 0)
+        for (int k = 0; k < 6; ++k)
+            part[((size_t)blockIdx.x * C + c) * 6 + k] = red[0][c][k] + red[1][c][k] + red[2][c][k] + red[3][c][k];
+}
+
+// y_c(node 4t+p) = x_c(node) + 0.1 Y[tok][p*3 + c]
+__global__ void __launch_bounds__(256) k_head_out(Shape s, const double *x, const float *Y, double *y) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= 3 * s.B * s.L) return;
+    const int c = e / (s.B * s.L), node = e % (s.B * s.L);
+    const int b = node / s.L, l = node % s.L, t = l / PATCH, p = l % PATCH;
+    y[e] = x[e] + OUT_SCALE * (double)Y[(size_t)(b * s.T + t) * 32 + p * 3 + c];
+}
+
+// dY = 2 (Y - (target - x)/0.1) / (M*12) as BF16 [M][16] (cols >= 12 zero);
+// loss partial per workgroup.
+__global__ void __launch_bounds__(256) k_loss(Shape s, const double *x, const double *target,
+                                              const float *Y, __bf16 *dY, float *lpart) {
+    __shared__ float red[256];
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    float sq = 0.0f;
+    if (e < s.M * 16) {
+        const int tok = e / 16, j = e % 16;
+        float d = 0.0f;
+        if (j < FOUT) {
+            const int p = j / 3, c = j % 3, b = tok / s.T, t = tok % s.T;
+            const size_t idx = (size_t)c * s.B * s.L + (size_t)b * s.L + t * PATCH + p;
+            const float tn = (float)((target[idx] - x[idx]) / OUT_SCALE);
+            const float diff = Y[(size_t)tok * 32 + j] - tn;
+            sq = diff * diff;
+            d = 2.0f * diff / ((float)s.M * FOUT);
+        }
+        dY[e] = to_bf16(d);
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_loss_final(const float *lpart, int n, int count, float *loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float s = 0.0f;
+    for (int i = 0; i < n; ++i) s += lpart[i];
+    *loss = s / (float)count;
+}
+
+// [c][6] partial sums -> kc[c][5], bc[c] gradients
+__global__ void __launch_bounds__(64) k_conv_scatter(const float *src, float *kcg, float *bcg) {
+    const int c = threadIdx.x;
+    for (int t = 0; t < TAPS; ++t) kcg[c * TAPS + t] = src[c * 6 + t];
+    bcg[c] = src[c * 6 + 5];
+}
+
+// dZ1 = bf16(dA1 * gelu'(Z1))
+__global__ void __launch_bounds__(256) k_gelu_bwd(int n, const float *dA1, const float *Z1, __bf16 *dZ1) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < n) dZ1[e] = to_bf16(dA1[e] * gelu_grad(Z1[e]));
+}
+
+// ---------------------------------------------------------------------------
+// Parameters: BF16 copies (with transposes and zero padding), Adam
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_pack(const float *P, __bf16 *Q) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= QTOTAL) return;
+    float v = 0.0f;
+    if (e < Q_BLK) {
+        v = P[P_WE + e];
+    } else if (e < Q_WHP) {
+        const int b = (e - Q_BLK) / QBLK, r = (e - Q_BLK) % QBLK;
+        const float *blk = P + P_BLK + b * BLK;
+        if (r < Q_W1T) v = blk[B_W1 + r];                                        // W1 [128][64]
+        else if (r < Q_W2) { const int i = r - Q_W1T, k = i / HID, n = i % HID;  // W1t [64][128]
+            v = blk[B_W1 + n * C + k]; }
+        else if (r < Q_W2T) v = blk[B_W2 + (r - Q_W2)];                          // W2 [64][128]
+        else { const int i = r - Q_W2T, k = i / C, n = i % C;                    // W2t [128][64]
+            v = blk[B_W2 + n * HID + k]; }
+    } else if (e < Q_WHTP) {
+        const int i = e - Q_WHP, n = i / C, k = i % C;                           // Whp [32][64]
+        v = n < FOUT ? P[P_WH + n * C + k] : 0.0f;
+    } else {
+        const int i = e - Q_WHTP, k = i / 16, n = i % 16;                        // Whtp [64][16]
+        v = n < FOUT ? P[P_WH + n * C + k] : 0.0f;
+    }
+    Q[e] = to_bf16(v);
+}
+
+__global__ void __launch_bounds__(256) k_adam(int n, float *p, float *m, float *v, const float *gr,
+                                              float lr, float b1, float b2, float eps, float c1,
+                                              float c2) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float g = gr[e];
+    const float mm = b1 * m[e] + (1.0f - b1) * g;
+    const float vv = b2 * v[e] + (1.0f - b2) * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Admission check, lift, merge
+// ---------------------------------------------------------------------------
+struct CheckArgs {
+    int B, L;
+    const double *x, *y, *gamma;
+    double tol_m, tol_p, tol_e;
+    int32_t *accept;
+};
+
+// One workgroup per tube: FP64 totals of x and y in a fixed order.
+__global__ void __launch_bounds__(256) k_check(CheckArgs a) {
+    __shared__ double red[256][7];
+    __shared__ int bad_s;
+    const int b = blockIdx.x;
+    const double n = 2.0 / (a.gamma[b] - 1.0) - 1.0;
+    const size_t BL = (size_t)a.B * a.L;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // Mx, Px, Ex, My, Py, Ey, Tmax
+    int bad = 0;
+    for (int l = threadIdx.x; l < a.L; l += 256) {
+        const size_t i = (size_t)b * a.L + l;
+        const double rx = a.x[i], ux = a.x[BL + i], Tx = a.x[2 * BL + i];
+        const double ry = a.y[i], uy = a.y[BL + i], Ty = a.y[2 * BL + i];
+        acc[0] += rx;
+        acc[1] += rx * ux;
+        acc[2] += rx * (0.5 * ux * ux + 0.5 * (1.0 + n) * Tx);
+        acc[3] += ry;
+        acc[4] += ry * uy;
+        acc[5] += ry * (0.5 * uy * uy + 0.5 * (1.0 + n) * Ty);
+        acc[6] = fmax(acc[6], Tx);
+        if (!__builtin_isfinite(ry) || !__builtin_isfinite(uy) || !__builtin_isfinite(Ty) || ry <= 0.0 ||
+            Ty <= 0.0)
+            bad = 1;
+    }
+    if (threadIdx.x == 0) bad_s = 0;
+    for (int k = 0; k < 7; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    if (bad) atomicOr(&bad_s, 1);
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 7; ++k)
+                red[threadIdx.x][k] = k == 6 ? fmax(red[threadIdx.x][k], red[threadIdx.x + h][k])
+                                             : red[threadIdx.x][k] + red[threadIdx.x + h][k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double Mx = red[0][0], Px = red[0][1], Ex = red[0][2];
+        const double My = red[0][3], Py = red[0][4], Ey = red[0][5], Tm = red[0][6];
+        bool ok = !bad_s && __builtin_isfinite(My) && __builtin_isfinite(Ey);
+        ok = ok && fabs(My - Mx) <= a.tol_m * fabs(Mx);
+        ok = ok && fabs(Py - Px) <= a.tol_p * fabs(Mx) * sqrt(Tm > 0.0 ? Tm : 0.0);
+        ok = ok && fabs(Ey - Ex) <= a.tol_e * fabs(Ex);
+        a.accept[b] = ok ? 1 : 0;
+    }
+}
+
+// Equilibrium populations of x for rejected tubes without live populations;
+// nsteps per tube.
+__global__ void __launch_bounds__(256) k_lift(int B, int L, const double *x, const int32_t *accept,
+                                              const int32_t *valid, float *f0, float *g0,
+                                              int64_t *nsteps) {
+    const size_t BL = (size_t)B * L;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < (size_t)B) nsteps[i] = accept[i] ? 0 : LBM_SUR_K;
+    if (i >= BL) return;
+    const int b = (int)(i / L);
+    if (accept[b] || valid[b]) return;
+    const double uu[3] = {x[BL + i], 0.0, 0.0};
+    const FeqCoef<double> fc = feq_coef<double, 1>(x[i], uu, x[2 * BL + i]);
+    static_for<0, 7>([&](auto I) {
+        constexpr int k = decltype(I)::value;
+        f0[(size_t)k * BL + i] = (float)feq_dir<double, 1, k>(fc);
+    });
+    const GeqCoef<double> gc = geq_coef<double>(x[2 * BL + i]);
+    static_for<0, 7>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        g0[(size_t)j * BL + i] = (float)geq_dir<double, j>(gc);
+    });
+}
+
+__global__ void __launch_bounds__(256) k_merge(int B, int L, const int32_t *accept, const double *y,
+                                               const double *z, double *out, int32_t *valid) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t BL = (size_t)B * L;
+    if (e >= 3 * BL) return;
+    const int b = (int)((e % BL) / L);
+    out[e] = accept[b] ? y[e] : z[e];
+    if (e < BL && e % L == 0) valid[b] = accept[b] ? 0 : 1;
+}
+
+}  // namespace sur
+}  // namespace lbmx
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace {
+using namespace lbmx::sur;
+
+lbm_status sfail(lbm_status s, const std::string &m) {
+    lbmx::set_error(m.c_str());
+    return s;
+}
+
+struct WS {
+    size_t off = 0;
+    char *base;
+    explicit WS(void *b) : base((char *)b) {}
+    template <typename T> T *take(size_t n) {
+        off = (off + 255) / 256 * 256;
+        T *p = (T *)(base + off);
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+struct Bufs {
+    __bf16 *X, *dY, *dZ1, *A1[NB];
+    float *H[NB + 1], *Hc[NB], *Z1[NB], *Y, *dH, *dA1, *dHc, *part, *bpart, *lpart;
+};
+
+size_t nchunk128(int M) { return (size_t)(M + 127) / 128; }
+
+Bufs carve(const lbm_sur_desc *d, size_t *bytes) {
+    const int M = d->batch * d->length / PATCH;
+    WS w(d->workspace);
+    Bufs b;
+    b.X = w.take<__bf16>((size_t)M * FIN);
+    for (int i = 0; i <= NB; ++i) b.H[i] = w.take<float>((size_t)M * C);
+    for (int i = 0; i < NB; ++i) {
+        b.Hc[i] = w.take<float>((size_t)M * C);
+        b.Z1[i] = w.take<float>((size_t)M * HID);
+        b.A1[i] = w.take<__bf16>((size_t)M * HID);
+    }
+    b.Y = w.take<float>((size_t)M * 32);
+    b.dY = w.take<__bf16>((size_t)M * 16);
+    b.dH = w.take<float>((size_t)M * C);
+    b.dA1 = w.take<float>((size_t)M * HID);
+    b.dZ1 = w.take<__bf16>((size_t)M * HID);
+    b.dHc = w.take<float>((size_t)M * C);
+    const size_t nch = nchunk128(M);
+    b.part = w.take<float>(nch * HID * HID > (size_t)(M / 64 + 1) * C * 6 ? nch * HID * HID
+                                                                          : (size_t)(M / 64 + 1) * C * 6);
+    b.bpart = w.take<float>(nch * HID);
+    b.lpart = w.take<float>((size_t)M * 16 / 256 + 1);
+    *bytes = w.off + 256;
+    return b;
+}
+
+lbm_status svalidate(const lbm_sur_desc *d) {
+    if (!d) return sfail(LBM_EINVAL, "surrogate descriptor is NULL");
+    if (d->abi_version != LBM_ABI_VERSION) return sfail(LBM_EINVAL, "abi_version mismatch");
+    if (d->batch < 1 || d->length < 128 || d->length % 128)
+        return sfail(LBM_EINVAL, "batch >= 1 and length a positive multiple of 128 required");
+    if ((long long)d->batch * d->length >= (1LL << 31)) return sfail(LBM_EINVAL, "batch * length too large");
+    return LBM_OK;
+}
+
+unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
+
+template <int N, int K, bool AF32, int EPI>
+void gemm(hipStream_t s, int M, int nvalid, const void *A, const __bf16 *Bt, const float *bias,
+          const float *R, float *out, __bf16 *out_bf, float *pre) {
+    GemmArgs g{M, nvalid, A, Bt, bias, R, out, out_bf, pre};
+    hipLaunchKernelGGL((k_gemm<N, K, AF32, EPI>), dim3((M + 127) / 128), dim3(256), 0, s, g);
+}
+
+template <int N, int K, int NA, int KB, bool AF32, bool BF32>
+void wgrad(hipStream_t s, int M, int Nv, int Kv, const void *A, const void *B, float *part, float *bpart,
+           float *gW, float *gb) {
+    const int nch = (int)nchunk128(M);
+    WgArgs g{M, Nv, Kv, A, B, part, gb ? bpart : nullptr};
+    hipLaunchKernelGGL((k_wgrad<N, K, NA, KB, AF32, BF32>), dim3(nch), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk((size_t)Nv * Kv)), dim3(256), 0, s, part, nch, Nv * Kv, gW, 0);
+    if (gb) hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(Nv)), dim3(256), 0, s, bpart, nch, Nv, gb, 0);
+}
+
+// Forward through the network; keeps every activation needed by backward.
+void forward(const lbm_sur_desc *d, const Bufs &b, const double *x, const double *gamma, hipStream_t s) {
+    const Shape sh{d->batch, d->length, d->length / PATCH, d->batch * d->length / PATCH};
+    const int M = sh.M;
+    const float *P = d->params;
+    const __bf16 *Q = (const __bf16 *)d->params_bf16;
+    hipLaunchKernelGGL(k_patchify, dim3(nblk((size_t)M * FIN)), dim3(256), 0, s, sh, x, gamma, b.X);
+    gemm<64, 16, false, EPI_BIAS | EPI_F32>(s, M, C, b.X, Q + Q_WE, P + P_BE, nullptr, b.H[0], nullptr, nullptr);
+    for (int k = 0; k < NB; ++k) {
+        const float *blk = P + P_BLK + k * BLK;
+        const __bf16 *qb = Q + Q_BLK + k * QBLK;
+        hipLaunchKernelGGL(k_conv_fwd, dim3(nblk((size_t)M * C)), dim3(256), 0, s, sh, b.H[k], blk + B_KC,
+                           blk + B_BC, b.Hc[k]);
+        gemm<128, 64, true, EPI_BIAS | EPI_GELU | EPI_BF16>(s, M, HID, b.Hc[k], qb + Q_W1, blk + B_B1, nullptr,
+                                                            nullptr, b.A1[k], b.Z1[k]);
+        gemm<64, 128, false, EPI_BIAS | EPI_RES | EPI_F32>(s, M, C, b.A1[k], qb + Q_W2, blk + B_B2, b.Hc[k],
+                                                           b.H[k + 1], nullptr, nullptr);
+    }
+    gemm<32, 64, true, EPI_BIAS | EPI_F32>(s, M, FOUT, b.H[NB], Q + Q_WHP, P + P_BH, nullptr, b.Y, nullptr,
+                                           nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_sur_bf16_bytes(void) { return (size_t)QTOTAL * 2; }
+
+size_t lbm_sur_workspace_bytes(const lbm_sur_desc *desc) {
+    if (!desc || desc->batch < 1 || desc->length < 128) return 0;
+    lbm_sur_desc d = *desc;
+    d.workspace = nullptr;
+    size_t bytes = 0;
+    carve(&d, &bytes);
+    return bytes;
+}
+
+lbm_status lbm_sur_pack(const lbm_sur_desc *d, void *stream) {
+    lbm_status st = svalidate(d);
+    if (st) return st;
+    if (!d->params || !d->params_bf16) return sfail(LBM_EINVAL, "params and params_bf16 required");
+    hipLaunchKernelGGL(k_pack, dim3(nblk(QTOTAL)), dim3(256), 0, (hipStream_t)stream, d->params,
+                       (__bf16 *)d->params_bf16);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
+}
+
+lbm_status lbm_sur_forward(const lbm_sur_desc *d, const double *x, const double *gamma, double *y,
+                           void *stream) {
+    lbm_status st = svalidate(d);
+    if (st) return st;
+    if (!d->params || !d->params_bf16 || !d->workspace || !x || !gamma || !y)
+        return sfail(LBM_EINVAL, "NULL argument");
+    if (x == y) return sfail(LBM_EINVAL, "y may not alias x");
+    hipStream_t s = (hipStream_t)stream;
+    size_t bytes;
+    const Bufs b = carve(d, &bytes);
+    forward(d, b, x, gamma, s);
+    const Shape sh{d->batch, d->length, d->length / PATCH, d->batch * d->length / PATCH};
+    hipLaunchKernelGGL(k_head_out, dim3(nblk((size_t)3 * d->batch * d->length)), dim3(256), 0, s, sh, x, b.Y, y);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
+}
+
+lbm_status lbm_sur_backward(const lbm_sur_desc *d, const double *x, const double *gamma,
+                            const double *target, float *grads, float *loss, void *stream) {
+    lbm_status st = svalidate(d);
+    if (st) return st;
+    if (!d->params || !d->params_bf16 || !d->workspace || !x || !gamma || !target || !grads || !loss)
+        return sfail(LBM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    size_t bytes;
+    const Bufs b = carve(d, &bytes);
+    forward(d, b, x, gamma, s);
+    const Shape sh{d->batch, d->length, d->length / PATCH, d->batch * d->length / PATCH};
+    const int M = sh.M;
+    const __bf16 *Q = (const __bf16 *)d->params_bf16;
+    const float *P = d->params;
+    const unsigned nl = nblk((size_t)M * 16);
+    hipLaunchKernelGGL(k_loss, dim3(nl), dim3(256), 0, s, sh, x, target, b.Y, b.dY, b.lpart);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, b.lpart, (int)nl, M * FOUT, loss);
+    // head
+    wgrad<32, 64, 16, 64, false, true>(s, M, FOUT, C, b.dY, b.H[NB], b.part, b.bpart, grads + P_WH, grads + P_BH);
+    gemm<64, 16, false, EPI_F32>(s, M, C, b.dY, Q + Q_WHTP, nullptr, nullptr, b.dH, nullptr, nullptr);
+    for (int k = NB - 1; k >= 0; --k) {
+        const float *blk = P + P_BLK + k * BLK;
+        float *gblk = grads + P_BLK + k * BLK;
+        const __bf16 *qb = Q + Q_BLK + k * QBLK;
+        // dA1 = dO W2 ; dZ1 = dA1 gelu'(Z1)
+        gemm<128, 64, true, EPI_F32>(s, M, HID, b.dH, qb + Q_W2T, nullptr, nullptr, b.dA1, nullptr, nullptr);
+        hipLaunchKernelGGL(k_gelu_bwd, dim3(nblk((size_t)M * HID)), dim3(256), 0, s, M * HID, b.dA1, b.Z1[k],
+                           b.dZ1);
+        wgrad<64, 128, 64, 128, true, false>(s, M, C, HID, b.dH, b.A1[k], b.part, b.bpart, gblk + B_W2,
+                                             gblk + B_B2);
+        wgrad<128, 64, 128, 64, false, true>(s, M, HID, C, b.dZ1, b.Hc[k], b.part, b.bpart, gblk + B_W1,
+                                             gblk + B_B1);
+        // dHc = dO + dZ1 W1 ; dH = dHc + conv^T(dHc)
+        gemm<64, 128, false, EPI_RES | EPI_F32>(s, M, C, b.dZ1, qb + Q_W1T, nullptr, b.dH, b.dHc, nullptr,
+                                                nullptr);
+        const unsigned nc = (unsigned)((M + 63) / 64);
+        hipLaunchKernelGGL(k_conv_bwd, dim3(nc), dim3(256), 0, s, sh, b.dHc, b.H[k], blk + B_KC, b.dH, b.part);
+        // taps and bias of the convolution: part[wg][c][6] -> [c][6] -> kc, bc
+        hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(C * 6)), dim3(256), 0, s, b.part, (int)nc, C * 6, b.bpart, 0);
+        hipLaunchKernelGGL(k_conv_scatter, dim3(1), dim3(64), 0, s, b.bpart, gblk + B_KC, gblk + B_BC);
+    }
+    wgrad<64, 32, 64, 16, true, false>(s, M, C, FIN, b.dH, b.X, b.part, b.bpart, grads + P_WE, grads + P_BE);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
+}
+
+lbm_status lbm_sur_adam(const lbm_sur_desc *d, float *params, float *m, float *v, const float *grads, float lr,
+                        float beta1, float beta2, float eps, int64_t step, void *stream) {
+    lbm_status st = svalidate(d);
+    if (st) return st;
+    if (!params || !m || !v || !grads || step < 1) return sfail(LBM_EINVAL, "bad Adam arguments");
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_adam, dim3(nblk(NPARAMS)), dim3(256), 0, s, NPARAMS, params, m, v, grads, lr, beta1,
+                       beta2, eps, c1, c2);
+    hipLaunchKernelGGL(k_pack, dim3(nblk(QTOTAL)), dim3(256), 0, s, params, (__bf16 *)d->params_bf16);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
+}
+
+lbm_status lbm_sur_check(const lbm_sur_desc *d, const double *x, const double *y, const double *gamma,
+                         double tol_mass, double tol_mom, double tol_energy, int32_t *accept, void *stream) {
+    lbm_status st = svalidate(d);
+    if (st) return st;
+    if (!x || !y || !gamma || !accept) return sfail(LBM_EINVAL, "NULL argument");
+    CheckArgs a{d->batch, d->length, x, y, gamma, tol_mass, tol_mom, tol_energy, accept};
+    hipLaunchKernelGGL(k_check, dim3(d->batch), dim3(256), 0, (hipStream_t)stream, a);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
+}
+
+lbm_status lbm_sur_lift(const lbm_sur_desc *d, const double *x, const int32_t *accept, const int32_t *valid,
+                        void *f0, void *g0, int64_t *nsteps, void *stream) {
+    lbm_status st = svalidate(d);
+    if (st) return st;
+    if (!x || !accept || !valid || !f0 || !g0 || !nsteps) return sfail(LBM_EINVAL, "NULL argument");
+    const size_t BL = (size_t)d->batch * d->length;
+    hipLaunchKernelGGL(k_lift, dim3(nblk(BL > (size_t)d->batch ? BL : d->batch)), dim3(256), 0, (hipStream_t)stream,
+                       d->batch, d->length, x, accept, valid, (float *)f0, (float *)g0, nsteps);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
+}
+
+lbm_status lbm_sur_merge(const lbm_sur_desc *d, const int32_t *accept, const double *y, const double *z,
+                         double *out, int32_t *valid, void *stream) {
+    lbm_status st = svalidate(d);
+    if (st) return st;
+    if (!accept || !y || !z || !out || !valid) return sfail(LBM_EINVAL, "NULL argument");
+    const size_t n = (size_t)3 * d->batch * d->length;
+    hipLaunchKernelGGL(k_merge, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, d->batch, d->length, accept,
+                       y, z, out, valid);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
+}
+
+}  // extern "C"
