@@ -55,7 +55,7 @@ size_t pop_bytes(int dtype) { return dtype == LBM_F32 ? 4 : 8; }
 void default_tile(int dim, int tile[3]) {
     tile[2] = 1;
     if (dim == 1) { tile[0] = 256; tile[1] = 1; }
-    else if (dim == 2) { tile[0] = 64; tile[1] = 4; }
+    else if (dim == 2) { tile[0] = 256; tile[1] = 1; }
     else { tile[0] = 64; tile[1] = 1; }
 }
 

@@ -1,0 +1,129 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times, on sampled outputs the oracle recomputes node by node: the
+value of a node after k steps depends only on the nodes within 3k of it, so
+the oracle steps a window around each sampled node (open edges; their error
+reaches 3 nodes per step inward and never the centre)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _window(shape, center, radius):
+    """Flat indices (x fastest) of the periodic window around center."""
+    axes = [(np.arange(c - radius, c + radius + 1) % n) for c, n in zip(center, shape)]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")  # z, y, x
+    idx = np.zeros(grids[0].shape, dtype=np.int64)
+    mul = 1
+    for d, n in enumerate(shape):
+        idx += grids[len(shape) - 1 - d] * mul
+        mul *= n
+    return idx.reshape(-1)
+
+
+def _sampled_check(shape, kind, fields, n_rot, tau, steps, gpu, samples, radius):
+    rho, u, T = fields
+    D = len(shape)
+    w = 2 * radius + 1
+    G = oracle.Grid(kind, (w,) * D, bc=(oracle.OPEN,) * D, n_rot=n_rot, tau=tau)
+    centre = (w ** D) // 2
+    worst = 0.0
+    for c in samples:
+        idx = _window(shape, c, radius)
+        f, g = G.init_eq(rho[idx], u[:, idx], T[idx])
+        G.step(f, g, steps)
+        r_o, u_o, T_o, _ = G.moments(f, g)
+        node = sum(c[d] * int(np.prod(shape[:d])) for d in range(D))
+        for a, b in ((gpu[0][node], r_o[centre]), (gpu[2][node], T_o[centre])):
+            worst = max(worst, abs(a - b))
+        for d in range(D):
+            worst = max(worst, abs(gpu[1][d, node] - u_o[d, centre]))
+    return worst
+
+
+def test_periodic_2d_full_size_sampled(torch_cuda):
+    """1024 x 1024 D2Q49 FP32, default launch shape and graph replay."""
+    from paper_1606_06107_amd import Sim
+    announce("2-D 1024^2 sampled")
+    w = workloads.Periodic2D()
+    fields = w.fields()
+    sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch_cuda.float32).init(*fields)
+    sim.step(2)
+    gpu = [a.cpu().numpy() for a in sim.moments()[:3]]
+    rng = np.random.default_rng(11)
+    samples = [tuple(int(v) for v in rng.integers(0, 1024, 2)) for _ in range(24)]
+    samples += [(0, 0), (1023, 1023), (0, 1023)]
+    err = _sampled_check((w.nx, w.ny), oracle.D2Q49, fields, w.n_rot, w.tau, 2, gpu, samples, 8)
+    assert err <= FP32_TOL, err
+
+
+def test_periodic_2d_full_size_conservation(torch_cuda):
+    """Properties at any size: 1000 steps of the full 1024^2 run stay finite
+    and conserve mass and momentum to FP32 storage rounding."""
+    from paper_1606_06107_amd import Sim
+    announce("2-D 1024^2 conservation")
+    w = workloads.Periodic2D()
+    sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch_cuda.float32).init(*w.fields())
+    t0 = sim.moments(fields=False)[3].cpu().numpy()
+    sim.step(1000)
+    rho, _, T, t1 = (a.cpu().numpy() if a is not None else None for a in sim.moments())
+    assert np.isfinite(rho).all() and np.isfinite(T).all()
+    assert abs(t1[0] - t0[0]) <= 1e-8 * t0[0]
+    assert np.abs(t1[1:3] - t0[1:3]).max() <= 1e-8 * t0[0]
+
+
+def test_turbulence_3d_full_size_sampled(torch_cuda):
+    """256^3 D3Q343 FP32 (gamma = 1.4), one step, default launch shape."""
+    from paper_1606_06107_amd import Sim
+    announce("3-D 256^3 sampled")
+    w = workloads.Turbulence3D()
+    fields = w.fields()
+    sim = Sim((w.n,) * 3, n_rot=w.n_rot, tau=w.tau, dtype=torch_cuda.float32).init(*fields)
+    sim.step(1)
+    gpu = [a.cpu().numpy() for a in sim.moments(totals=False)[:3]]
+    del sim
+    rng = np.random.default_rng(12)
+    samples = [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(6)] + [(0, 0, 0), (255, 0, 255)]
+    err = _sampled_check((w.n,) * 3, oracle.D3Q343, fields, w.n_rot, w.tau, 1, gpu, samples, 4)
+    assert err <= FP32_TOL, err
+
+
+def test_batched_tubes_full_size_sampled(torch_cuda):
+    """The 4096-tube batch in one persistent launch (FP64); sampled stable
+    tubes recomputed by the oracle over their whole step count."""
+    from paper_1606_06107_amd import Batch
+    announce("4096 tubes sampled")
+    bt = workloads.batched_tubes(4096, seed=0)
+    b = Batch(bt.lengths, bt.n_rot, bt.tau, bt.steps, dtype=torch_cuda.float64).init(bt.rho, bt.u[0], bt.T)
+    b.step()
+    st = b.status.cpu().numpy()
+    done = b.steps_done.cpu().numpy()
+    assert ((st == 0) == (done == bt.steps)).all()  # completed exactly the healthy tubes
+    rho = b.split(b.moments()[0])
+    ok = np.nonzero((st == 0) & (bt.lengths * bt.steps < 3e5))[0][:3]
+    assert len(ok) >= 2
+    for i in ok:
+        r0, u0, T0 = workloads.sod_tube(int(bt.lengths[i]), bt.left[i], bt.right[i])
+        G = oracle.Grid(oracle.D1Q7, (int(bt.lengths[i]),), bc=(oracle.OPEN,), n_rot=bt.n_rot[i], tau=bt.tau[i])
+        f, g = G.init_eq(r0, u0, T0)
+        G.step(f, g, int(bt.steps[i]))
+        ro = G.moments(f, g)[0]
+        # The kernels and the oracle round in different orders (~1e-16 per
+        # operation); over ~1000 steps through a strong shock these
+        # differences grow to ~1e-11 of the field (the smooth workloads and
+        # the 1000-step tube stay below 1e-12).
+        assert np.abs(rho[i] - ro).max() <= 2e-11 * np.abs(ro).max(), i
