@@ -8,7 +8,9 @@ FP64 every 100 steps (fused into the step).  One "step" = one time step of
 the whole grid.  Inputs are resident in HBM before timing.
 
 Prints ONE JSON line (rank 0).  --gpus N > 1 is not supported: this build
-runs on a single GPU.
+runs on a single GPU.  Besides the headline workload the line carries
+`extra` measurements of the other workloads (1-D tube, 3-D turbulence,
+batched tubes, learned surrogate vs plain LBM); --no-extras skips them.
 """
 from __future__ import annotations
 
@@ -47,6 +49,168 @@ def cpu_baseline(nx, ny, steps, threads):
                       f"{dt:.1f} s wall"}
 
 
+def _events(stream):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    return a, b
+
+
+def extra_tube_1d():
+    """The 1-D shock tube (1000 nodes, FP64, 1000 steps as one HIP graph)."""
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    w = workloads.tube_1d()
+    sim = Sim((w.N,), bc=["open"], n_rot=w.n_rot, tau=w.tau, dtype=torch.float64).init(*w.fields())
+    sim.step(w.steps)  # capture + warm
+    sim.init(*w.fields())
+    a, b = _events(sim.stream)
+    torch.cuda.synchronize()
+    a.record(sim.stream)
+    sim.step(w.steps)
+    b.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    return {"workload": "1-D tube 1000 nodes, D1Q7+D1Q7 FP64, 1000 steps", "ms_total": round(ms, 3),
+            "us_per_step": round(1000 * ms / w.steps, 2), "MLUPS": round(w.N * w.steps / ms / 1e3, 1)}
+
+
+def extra_3d(steps=10):
+    """256^3 decaying turbulence, D3Q343 + D1Q7 FP32, gamma = 1.4."""
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    w = workloads.Turbulence3D()
+    sim = Sim((w.n,) * 3, n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields())
+    sim.step(2)
+    a, b = _events(sim.stream)
+    torch.cuda.synchronize()
+    a.record(sim.stream)
+    sim.step(steps)
+    b.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    N = w.n ** 3
+    gbs = N * 2800 / (ms * 1e-3) / 1e9
+    T = sim.moments(totals=False)[2]
+    ok = bool(torch.isfinite(T).all().item())
+    del sim
+    return {"workload": "3-D 256^3 turbulence, D3Q343+D1Q7 FP32, gamma=1.4", "ms_per_step": round(ms, 3),
+            "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "finite": ok}
+
+
+def extra_batch(seed=0):
+    """4096 ragged shock tubes, one persistent launch, FP32 and FP64, with the
+    per-instance FP32-vs-FP64 relative L1 error of rho, u, T (Sec. VI)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd.autotune import tune_batch
+    bt = workloads.batched_tubes(4096, seed=seed)
+    sub = bt.subset(np.arange(0, 4096, 8))
+    (blk, sup), table = tune_batch(
+        lambda b_, s_: Batch(sub.lengths, sub.n_rot, sub.tau, sub.steps, block=b_, superstep=s_).init(
+            sub.rho, sub.u[0], sub.T), key_extra="tubes512-f32")
+    out = {"workload": "4096 tubes, L logU[256,8192] (sum 9.26M nodes), D1Q7+D1Q7, one persistent launch",
+           "autotuned_block_superstep": [blk, sup]}
+    fields = {}
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        kw = dict(block=blk, superstep=sup) if dt == torch.float32 else {}
+        b = Batch(bt.lengths, bt.n_rot, bt.tau, bt.steps, dtype=dt, **kw).init(bt.rho, bt.u[0], bt.T)
+        a, e = _events(b.stream)
+        torch.cuda.synchronize()
+        a.record(b.stream)
+        b.step()
+        e.record(b.stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e)
+        st = b.status.cpu().numpy()
+        done = b.steps_done.cpu().numpy()
+        work = float((bt.lengths * done).sum())
+        out[name] = {"ms": round(ms, 2), "node_steps": work, "MLUPS": round(work / ms / 1e3, 1),
+                     "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
+        r, u, T = b.moments()
+        fields[name] = (st, [b.split(x) for x in (r, u, T)])
+        del b
+    st32, f32 = fields["f32"]
+    st64, f64 = fields["f64"]
+    both = np.nonzero((st32 == 0) & (st64 == 0))[0]
+    errs = []
+    for i in both:
+        errs.append([float(np.abs(f32[k][i] - f64[k][i]).sum() / max(np.abs(f64[k][i]).sum(), 1e-300))
+                     for k in range(3)])
+    errs = np.array(errs) if errs else np.zeros((0, 3))
+    out["fp32_vs_fp64_rel_l1"] = {"instances": int(len(both)),
+                                  "median_rho_u_T": [float(v) for v in np.median(errs, 0)] if len(both) else None,
+                                  "max_rho_u_T": [float(v) for v in errs.max(0)] if len(both) else None}
+    return out
+
+
+def extra_surrogate(train_candidates=2048, test_candidates=2048, train_steps=800, calls=16):
+    """Learned surrogate vs plain LBM on held-out 4096-node tubes: 16 calls
+    of k = 16 steps (256 steps) with the admission check and plain-LBM
+    fallback; errors judged against the plain LBM run (Sec. VI relative L1)."""
+    import numpy as np
+    import torch
+
+    from paper_1606_06107_amd import Batch, Surrogate
+    from paper_1606_06107_amd import surrogate as SG
+    t0 = time.perf_counter()
+    bt = SG.stable_tubes(train_candidates, seed=0)
+    x, tg, gm = SG.make_pairs(bt, pairs_per_tube=8, seed=1)
+    sur = Surrogate(32, 4096)
+    sur.set_params(SG.init_params(0))
+    hist = SG.train(sur, x, tg, gm, steps=train_steps, lr=2e-3, log_every=train_steps // 4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, tg
+    te = SG.stable_tubes(test_candidates, seed=10 ** 6)
+    B = te.num
+    x0 = torch.as_tensor(np.stack([te.rho, te.u[0], te.T]).reshape(3, B, 4096), device="cuda")
+    gamma = torch.as_tensor(te.gamma, device="cuda")
+    plain = Batch(te.lengths, te.n_rot, te.tau, np.full(B, 16 * calls), dtype=torch.float32)
+    plain.init(te.rho, te.u[0], te.T).step()  # warm (graph capture)
+    plain.init(te.rho, te.u[0], te.T)
+    a, e = _events(plain.stream)
+    torch.cuda.synchronize()
+    a.record(plain.stream)
+    plain.step()
+    e.record(plain.stream)
+    torch.cuda.synchronize()
+    t_lbm = a.elapsed_time(e)
+    ref = SG.fields_of(plain)
+    surB = sur.shape_like(B)
+    fb = Batch(te.lengths, te.n_rot, te.tau, np.zeros(B, dtype=np.int64), dtype=torch.float32)
+    SG.rollout(surB, x0, gamma, fb, calls)  # warm
+    a, e = _events(plain.stream)
+    torch.cuda.synchronize()
+    a.record(plain.stream)
+    xr, acc = SG.rollout(surB, x0, gamma, fb, calls)
+    e.record(plain.stream)
+    torch.cuda.synchronize()
+    t_sur = a.elapsed_time(e)
+
+    def l1(p, q):
+        return (torch.abs(p - q).sum(-1) / torch.abs(q).sum(-1).clamp_min(1e-300)).mean(1).cpu().numpy()
+    err, err_id = l1(xr, ref), l1(x0, ref)
+    xn, _ = SG.rollout(surB, x0, gamma, fb, calls, fallback=False)
+    err_nf = l1(xn, ref)
+    accepted = int(acc.sum().item())
+    return {"workload": f"{B} held-out stable 4096-node tubes, {calls} calls x 16 steps",
+            "train": {"stable_tubes": int(bt.num), "pairs": int(bt.num * 8), "adam_steps": train_steps,
+                      "seconds": round(t_train, 2), "loss": hist},
+            "t_lbm_ms": round(t_lbm, 3), "t_surrogate_with_fallback_ms": round(t_sur, 3),
+            "speedup": round(t_lbm / t_sur, 3), "accepted_fraction": round(accepted / (B * calls), 4),
+            "rel_l1_rho_u_T": [round(float(v), 5) for v in err],
+            "rel_l1_no_fallback": [round(float(v), 5) for v in err_nf],
+            "rel_l1_identity": [round(float(v), 5) for v in err_id]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +222,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--tile", type=str, default="")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="first run a plain device copy of this many MB (5 times): the reference "
+                         "kernel for scaling HBM traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU "
@@ -71,12 +240,25 @@ def main():
     from paper_1606_06107_amd import Sim
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * 1024 * 1024 // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = workloads.Periodic2D(nx=args.nx, ny=args.ny)
     rho, u, T = w.fields()
     N = args.nx * args.ny
     sim = Sim((args.nx, args.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(rho, u, T)
+    tuned = None
     if args.tile:
         sim.set_tile(*[int(v) for v in args.tile.split("x")])
+    elif not args.no_autotune:
+        from paper_1606_06107_amd.autotune import tune_sim
+        tuned, _ = tune_sim(sim, steps=20, reps=2)
+        sim.init(rho, u, T)  # tuning advanced the state; start over
     total_steps = args.warmup + args.steps
     cap = total_steps // args.monitor_every + 2
     series = sim.set_monitor(args.monitor_every, cap)
@@ -124,13 +306,23 @@ def main():
                                f"nodes, FP32 populations / FP64 moments, gamma=1.4 (n=3), "
                                f"tau=1, 8-mode random fields at Mach 0.3, seed 0, "
                                f"FP64 totals every {args.monitor_every} steps",
-                   "nodes": N, "bytes_per_node_step": bytes_per_node},
+                   "nodes": N, "bytes_per_node_step": bytes_per_node,
+                   "tile": list(tuned) if tuned else args.tile or "default"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None},
         "checks": {"finite": finite, "mass_drift": mass_drift, "momentum_drift": mom_drift,
                    "energy_drift_n3": energy_drift, "wall_s": round(wall, 3)},
     }
+    del sim
+    if not args.no_extras:
+        extra = {}
+        for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d),
+                         ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
+            print(f"bench: {name}", file=sys.stderr, flush=True)
+            extra[name] = fn()
+            torch.cuda.empty_cache()
+        out["extra"] = extra
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
         out["cpu_baseline"] = cpu_baseline(args.nx, args.ny, args.cpu_steps, threads)
