@@ -24,6 +24,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters on a plain device copy of known
+# size (profiles/k_step_12_d2q49_1024x1024_fp32.md), valid only for the
+# kernel sources they were taken on (sha256 of the files below).
+TRAFFIC = {"bytes": 491_475_866, "nodes": 1024 * 1024, "tile": (256, 1),
+           "sha256": "4691d32227bf5e871542f7f10ab3be01fb64a9bf472e841c1a8184e4764b8771"}
+TRAFFIC_SOURCES = ("paper_1606_06107_amd/csrc/step_impl.hpp",
+                   "paper_1606_06107_amd/csrc/lbm_device.hpp",
+                   "paper_1606_06107_amd/csrc/step_12_f32.hip")
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 METRIC = "MLUPS & % HBM roofline; surrogate vs plain LBM speedup at <=1e-2 L1 error"
 
 
@@ -286,6 +307,10 @@ def main():
     energy_drift = float(abs(tot[3] - s[0, 3]) / s[0, 3])
     finite = bool(torch.isfinite(Tn).all().item())
 
+    used_tile = tuple(tuned) if tuned else (
+        tuple(int(v) for v in args.tile.split("x")) if args.tile else (256, 1))
+    traffic_ok = (kernel_sha() == TRAFFIC["sha256"] and N == TRAFFIC["nodes"]
+                  and used_tile == TRAFFIC["tile"])
     mlups = N / (ms_per_step * 1e-3) / 1e6
     bytes_per_node = 2 * (49 + 7) * 4  # read + write every population once
     achieved_gbs = N * bytes_per_node / (ms_per_step * 1e-3) / 1e9
@@ -310,7 +335,7 @@ def main():
                    "tile": list(tuned) if tuned else args.tile or "default"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": TRAFFIC["bytes"] if traffic_ok else None},
         "checks": {"finite": finite, "mass_drift": mass_drift, "momentum_drift": mom_drift,
                    "energy_drift_n3": energy_drift, "wall_s": round(wall, 3)},
     }
