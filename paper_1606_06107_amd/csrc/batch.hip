@@ -125,7 +125,7 @@ __device__ __forceinline__ void lds_node(const P *F, const P *G, int C, int x, i
     for (int j = 0; j < 7; ++j)
         if (j != 3) M.er += double((j - 3) * (j - 3)) * (double)gv[j];
     double u[3] = {0.0, 0.0, 0.0}, Etot;
-    finish_moments<1>(M, n_rot, rho, u, T, Etot);
+    const double inv = finish_moments<1>(M, n_rot, rho, u, T, Etot);
 
     const P up[3] = {(P)u[0], P(0), P(0)};
     const FeqCoef<P> fc = feq_coef<P, 1>((P)rho, up, (P)T);
@@ -148,7 +148,7 @@ __device__ __forceinline__ void lds_node(const P *F, const P *G, int C, int x, i
             s1 += c * d[i];
             s2 += c * c * d[i];
         }
-        const double t2 = omega * (M.m1[0] * M.m1[0] / rho + rho * T / (kR * kR) - M.e2);
+        const double t2 = omega * (M.m1[0] * M.m1[0] * inv + rho * T * kInvR2 - M.e2);
         const double R1[3] = {-(double)s1, 0.0, 0.0};
         const Eps ep = eps_from_defects<1>(-(double)s0, R1, t2 - (double)s2);
         d[3] += (P)ep.e[0];
@@ -177,7 +177,7 @@ __device__ __forceinline__ void lds_node(const P *F, const P *G, int C, int x, i
             g0 += (double)gv[j];
         }
         double al, ga;
-        gfix_from_defects(omega * (1.0 - g0) - r0, omega * (T / (kR * kR) - M.er) - r2, al, ga);
+        gfix_from_defects(omega * (1.0 - g0) - r0, omega * (T * kInvR2 - M.er) - r2, al, ga);
 #pragma unroll
         for (int j = 0; j < 7; ++j)
             rl[j] += P(kW1[iabs(j - 3)]) * ((P)al + P((j - 3) * (j - 3)) * (P)ga);

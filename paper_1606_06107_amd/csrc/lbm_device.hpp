@@ -54,11 +54,25 @@ struct Mom {
     double m0, m1[3], e2, er;
 };
 
-template <int D> __device__ __forceinline__ void finish_moments(const Mom &M, double n_rot,
-                                                                double &rho, double u[3],
-                                                                double &T, double &Etot) {
+// 1/x for normal x to within about an ulp: the hardware estimate refined by
+// two Newton-Raphson steps r <- r + r (1 - x r) (each squares the relative
+// error).  A full IEEE division costs several times as many FP64 operations.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+constexpr double kInvR2 = 1.0 / (kR * kR);
+
+// Returns 1/rho.
+template <int D> __device__ __forceinline__ double finish_moments(const Mom &M, double n_rot,
+                                                                  double &rho, double u[3],
+                                                                  double &T, double &Etot) {
     rho = M.m0;
-    const double inv = 1.0 / rho;
+    const double inv = rcp64(rho);
     double mm = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -68,8 +82,9 @@ template <int D> __device__ __forceinline__ void finish_moments(const Mom &M, do
     const double Et = 0.5 * kR * kR * M.e2;
     const double rho_er = rho * 0.5 * n_rot * kR * kR * M.er;
     const double ke = 0.5 * kR * kR * mm * inv;
-    T = 2.0 / (D + n_rot) * (Et + rho_er - ke) * inv;
+    T = 2.0 * rcp64(D + n_rot) * (Et + rho_er - ke) * inv;
     Etot = Et + rho_er;
+    return inv;
 }
 
 // ---------------------------------------------------------------------------
@@ -147,10 +162,20 @@ template <typename P, int J> __device__ __forceinline__ P geq_dir(const GeqCoef<
 //   nu >= 0: nu (h[-2] - 6 h[-1] + 3 h[0] + 2 h[+1]) / 6
 //   nu <  0: nu (-h[+2] + 6 h[+1] - 3 h[0] - 2 h[-1]) / 6
 // ---------------------------------------------------------------------------
-template <typename P> __device__ __forceinline__ P upwind3(P nu, P hm2, P hm1, P h0, P hp1, P hp2) {
-    const P dp = (hm2 - P(6) * hm1 + P(3) * h0 + P(2) * hp1) * P(1.0 / 6.0);
-    const P dm = (-hp2 + P(6) * hp1 - P(3) * h0 - P(2) * hm1) * P(1.0 / 6.0);
+// Split form: the two one-sided differences do not depend on nu, so they can
+// be formed as soon as the stencil values arrive.
+template <typename P>
+__device__ __forceinline__ void upwind_diff(P hm2, P hm1, P h0, P hp1, P hp2, P &dp, P &dm) {
+    dp = (hm2 - P(6) * hm1 + P(3) * h0 + P(2) * hp1) * P(1.0 / 6.0);
+    dm = (-hp2 + P(6) * hp1 - P(3) * h0 - P(2) * hm1) * P(1.0 / 6.0);
+}
+template <typename P> __device__ __forceinline__ P upwind_apply(P nu, P dp, P dm) {
     return nu * (nu >= P(0) ? dp : dm);
+}
+template <typename P> __device__ __forceinline__ P upwind3(P nu, P hm2, P hm1, P h0, P hp1, P hp2) {
+    P dp, dm;
+    upwind_diff<P>(hm2, hm1, h0, hp1, hp2, dp, dm);
+    return upwind_apply<P>(nu, dp, dm);
 }
 
 // Periodic wrap or clamp of an arbitrary coordinate (tile halos may reach
@@ -173,6 +198,41 @@ template <typename P> __device__ __forceinline__ void stp(void *base, int i, uin
                                                          uint32_t off, P v) {
     char *p = reinterpret_cast<char *>(base) + (size_t)i * N * sizeof(P);
     *reinterpret_cast<P *>(p + off) = v;
+}
+
+// Streaming variants for the populations, which every time step reads once
+// and writes once: loads carry the non-temporal hint and stores the sc1
+// cache policy, issued as raw buffer operations on a descriptor spanning the
+// population's row (out-of-range offsets read 0 / drop, never fault).  On
+// gfx950 this pair keeps the ping-pong working set from thrashing L2 and the
+// memory-side cache; measured on the pull pattern of a D2Q49 + D1Q7 step it
+// is ~11 % faster than the default policy.
+constexpr int kCpolLoadStream = 2;    // nt
+constexpr int kCpolStoreStream = 16;  // sc1
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void *base, int i, uint32_t N,
+                                                           uint32_t sz) {
+    const char *p = reinterpret_cast<const char *>(base) + (size_t)i * N * sz;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), 0, (int)(N * sz), kRsrcWord3);
+}
+template <typename P> __device__ __forceinline__ P ldp_stream(const void *base, int i, uint32_t N,
+                                                             uint32_t off) {
+    const __amdgpu_buffer_rsrc_t r = pop_rsrc(base, i, N, sizeof(P));
+    if constexpr (sizeof(P) == 4)
+        return __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, kCpolLoadStream));
+    else
+        return __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, kCpolLoadStream));
+}
+template <typename P> __device__ __forceinline__ void stp_stream(void *base, int i, uint32_t N,
+                                                                uint32_t off, P v) {
+    const __amdgpu_buffer_rsrc_t r = pop_rsrc(base, i, N, sizeof(P));
+    if constexpr (sizeof(P) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
+                                              kCpolStoreStream);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r,
+            (int)off, 0, kCpolStoreStream);
 }
 
 // Equilibrium of the direction pair (c, -c): with a = c.ru,
@@ -231,8 +291,9 @@ template <int D> __device__ __forceinline__ Eps eps_from_defects(double R0, cons
     x.e[0] = R0 - R2;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        x.e[1 + 2 * a] = a < D ? R2 / (2.0 * D) - 0.5 * R1[a] : 0.0;
-        x.e[2 + 2 * a] = a < D ? R2 / (2.0 * D) + 0.5 * R1[a] : 0.0;
+        constexpr double inv2d = 1.0 / (2.0 * D);
+        x.e[1 + 2 * a] = a < D ? R2 * inv2d - 0.5 * R1[a] : 0.0;
+        x.e[2 + 2 * a] = a < D ? R2 * inv2d + 0.5 * R1[a] : 0.0;
     }
     return x;
 }
@@ -241,9 +302,9 @@ template <int D> __device__ __forceinline__ Eps eps_from_defects(double R0, cons
 // increment w_j (alpha + gamma j^2) removes the defects of sum_j and sum_j j^2.
 __device__ __forceinline__ void gfix_from_defects(double d0, double d2, double &alpha,
                                                   double &gamma) {
-    constexpr double r2 = kR * kR;
-    gamma = (d2 - d0 / r2) * r2 * r2 / 2.0;
-    alpha = d0 - gamma / r2;
+    constexpr double r4h = 0.5 * kR * kR * kR * kR;
+    gamma = (d2 - d0 * kInvR2) * r4h;
+    alpha = d0 - gamma * kInvR2;
 }
 
 // Neighbour coordinate along one axis: periodic wrap (n >= 3, |d| <= 3) or

@@ -12,6 +12,9 @@
 // Populations are SoA [Q][N], node index x fastest.  Right after
 // initialisation f is stored streamed (`streamed` = 1, read in place).
 //
+// Populations go through the streaming load/store forms (non-temporal
+// loads, sc1 stores); the rotational stencil neighbours use cached loads.
+//
 // Kernel templates, included by the step_*.hip translation units that
 // instantiate and launch them.
 #pragma once
@@ -28,6 +31,45 @@ template <typename P> __device__ __forceinline__ const P *pop(const void *base, 
 template <typename P> __device__ __forceinline__ P *pop_w(void *base, int i, uint32_t N) {
     return reinterpret_cast<P *>(base) + (size_t)i * N;
 }
+
+// Byte-addressed population access: non-temporal loads of f (each value is
+// read once per step), cached loads of g (stencil neighbours are shared
+// between nodes) and plain stores.
+// `base` is uniform (population row), `off` the lane's 32-bit byte offset,
+// which gives SGPR-base + VGPR-offset addressing.
+template <typename P> __device__ __forceinline__ P ld_nt(const char *base, uint32_t off) {
+    return __builtin_nontemporal_load(reinterpret_cast<const P *>(base + off));
+}
+template <typename P> __device__ __forceinline__ P ld(const char *base, uint32_t off) {
+    return *reinterpret_cast<const P *>(base + off);
+}
+// Population stores: buffer form (explicit 32-bit lane offset) with the
+// streaming cache policy; `i` selects the population row.
+template <typename P> __device__ __forceinline__ void st(void *base, int i, uint32_t N,
+                                                        uint32_t off, P v) {
+    stp_stream<P>(base, i, N, off, v);
+}
+
+// Interior-wave form: buffer loads on a descriptor over population row `i`,
+// at lane offset `vo` plus a uniform row offset `so` plus an immediate.
+template <typename P, int CPOL>
+__device__ __forceinline__ P ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    if constexpr (sizeof(P) == 4)
+        return __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, CPOL));
+    else
+        return __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, CPOL));
+}
+
+// Lane shifts across the whole wave (DPP wave_shr:1 / wave_shl:1): lane l
+// receives v from lane l-1 (SHR) or l+1 (SHL); the lane with no source
+// (0, resp. 63) receives `fill`.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float fill, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill),
+                                                                 __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, false));
+}
+constexpr int kWaveShr1 = 0x138, kWaveShl1 = 0x130;
 
 // Fixed-order workgroup reduction of K doubles; thread 0 writes dst[0..K-1].
 template <int NT, int K>
@@ -58,8 +100,8 @@ __device__ __forceinline__ void block_totals(double (&v)[K], double *dst) {
 template <typename P>
 __device__ __forceinline__ void rot_relax_store(const P (&gv)[7], const P (&adv)[7],
                                                 const GeqCoef<P> &gc, P om, double omega,
-                                                double T, double er, bool valid, void *g_out,
-                                                uint32_t N, uint32_t off) {
+                                                double T, double er, void *g_out, uint32_t N,
+                                                uint32_t off) {
     if constexpr (sizeof(P) == 4) {
         double s0 = 0.0, s2 = 0.0, g0 = 0.0;
         P rl[7];
@@ -71,19 +113,17 @@ __device__ __forceinline__ void rot_relax_store(const P (&gv)[7], const P (&adv)
             if constexpr (j != 3) s2 += double((j - 3) * (j - 3)) * (double)rl[j];
         });
         double al, ga;
-        gfix_from_defects(omega * (1.0 - g0) - s0, omega * (T / (kR * kR) - er) - s2, al, ga);
+        gfix_from_defects(omega * (1.0 - g0) - s0, omega * (T * kInvR2 - er) - s2, al, ga);
         const P alp = (P)al, gam = (P)ga;
         static_for<0, 7>([&](auto J) {
             constexpr int j = decltype(J)::value;
             const P fixj = P(kW1[iabs(j - 3)]) * (alp + P((j - 3) * (j - 3)) * gam);
-            const P gn = gv[j] - adv[j] + (rl[j] + fixj);
-            if (valid) stp<P>(g_out, j, N, off, gn);
+            st<P>(g_out, j, N, off, gv[j] - adv[j] + (rl[j] + fixj));
         });
     } else {
         static_for<0, 7>([&](auto J) {
             constexpr int j = decltype(J)::value;
-            const P gn = gv[j] - adv[j] - om * (gv[j] - geq_dir<P, j>(gc));
-            if (valid) stp<P>(g_out, j, N, off, gn);
+            st<P>(g_out, j, N, off, gv[j] - adv[j] - om * (gv[j] - geq_dir<P, j>(gc)));
         });
     }
 }
@@ -106,28 +146,57 @@ __global__ void __launch_bounds__(TX *TY, sizeof(P) == 4 ? 4 : 2) k_step_12(Step
     const int lx = threadIdx.x % TX, ly = D >= 2 ? threadIdx.x / TX : 0;
     const int x = x0 + lx, y = y0 + ly;
     const bool valid = x < a.n0 && (D < 2 || y < a.n1);
+    // Lanes past a ragged edge work on the clamped node: they load, compute
+    // and store exactly what the lane of that node does (same bits to the
+    // same addresses), so stores need no guard.
     const int xc = x < a.n0 ? x : a.n0 - 1;
     const int yc = D >= 2 ? (y < a.n1 ? y : a.n1 - 1) : 0;
     const uint32_t N = a.N;
+    const size_t PS = (size_t)N * SZ;             // bytes per population row
+    const long RS = D >= 2 ? (long)a.n0 * SZ : 0;  // bytes per grid row
     const uint32_t nodeb = ((uint32_t)xc + (uint32_t)a.n0 * (uint32_t)yc) * SZ;
-    const int shift = 1 - a.streamed;
+    const char *fin = static_cast<const char *>(a.f_in);
+    const char *gin = static_cast<const char *>(a.g_in);
+    // Interior waves (every lane's +-3 neighbourhood inside the grid, gather
+    // from x - c): neighbour offsets are immediates (x) and uniform row
+    // offsets (y).  Other waves wrap or clamp per lane.
+    const bool inner = xc >= 3 && xc + 3 < a.n0 && (D < 2 || (yc >= 3 && yc + 3 < a.n1));
+    const bool fast = a.streamed == 0 && __all(inner);
+
+    // Interior lanes: vb = offset of (x-3, y-3) >= 0; row offsets in SGPRs.
+    const uint32_t vb = nodeb - 3u * SZ - (D >= 2 ? 3u * (uint32_t)RS : 0u);
+    uint32_t rowo[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) rowo[k] = D >= 2 ? (uint32_t)k * (uint32_t)RS : 0u;
+    // In FP32 interior waves that cover 64 consecutive x, the x neighbours of
+    // g come from adjacent lanes (DPP) plus four uniform halo values per j.
+    constexpr bool XDPP = F32 && TX % 64 == 0;
 
     // 1. Gather the streamed populations f_i(x) = f*_i(S(x - c_i)) (pull).
-    uint32_t ox[7], oy[7];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        ox[k] = (uint32_t)nb_coord(xc, -(k - 3) * shift, a.n0, a.open0) * SZ;
-        oy[k] = D >= 2 ? (uint32_t)nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * (uint32_t)a.n0 * SZ
-                       : 0u;
-    }
     P fv[Q];
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        fv[i] = ldp<P>(a.f_in, i, N, ox[cx_of(i) + 3] + (D >= 2 ? oy[cy_of(i) + 3] : 0u));
-    });
+    if (fast) {
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.f_in, i, N, SZ);
+            fv[i] = ld_buf<P, kCpolLoadStream>(r, vb + (3 - cx_of(i)) * SZ,
+                                               D >= 2 ? rowo[3 - cy_of(i)] : 0u);
+        });
+    } else {
+        const int shift = 1 - a.streamed;
+        uint32_t ox[7], oy[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            ox[k] = (uint32_t)nb_coord(xc, -(k - 3) * shift, a.n0, a.open0) * SZ;
+            oy[k] = D >= 2 ? (uint32_t)nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * (uint32_t)RS : 0u;
+        }
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fv[i] = ld_nt<P>(fin + i * PS, ox[cx_of(i) + 3] + (D >= 2 ? oy[cy_of(i) + 3] : 0u));
+        });
+    }
     P gv[7];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) gv[j] = ldp<P>(a.g_in, j, N, nodeb);
+    for (int j = 0; j < 7; ++j) gv[j] = ld<P>(gin + j * PS, nodeb);
 
     // 2. FP64 moments via per-column (cx) and per-row (cy) sums.
     double col[7] = {0, 0, 0, 0, 0, 0, 0}, row[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -153,7 +222,7 @@ __global__ void __launch_bounds__(TX *TY, sizeof(P) == 4 ? 4 : 2) k_step_12(Step
     for (int j = 0; j < 7; ++j)
         if (j != 3) M.er += double((j - 3) * (j - 3)) * (double)gv[j];
     double rho, u[3] = {0.0, 0.0, 0.0}, T, Etot;
-    finish_moments<D>(M, a.n_rot, rho, u, T, Etot);
+    const double inv = finish_moments<D>(M, a.n_rot, rho, u, T, Etot);
 
     if (a.partials) {  // uniform branch: totals of time t
         double tv[2 + D];
@@ -166,8 +235,8 @@ __global__ void __launch_bounds__(TX *TY, sizeof(P) == 4 ? 4 : 2) k_step_12(Step
 
     // 3. BGK relaxation towards the Hermite equilibrium; store post-collision.
     const P up[3] = {(P)u[0], (P)u[1], (P)u[2]};
-    const FeqCoef<P> fc = feq_coef<P, D>((P)rho, up, (P)T);
     const P om = (P)a.omega;
+    const FeqCoef<P> fc = feq_coef<P, D>((P)rho, up, (P)T);
     P dsp[NS];                               // increments of the special populations
     P cs[7] = {0, 0, 0, 0, 0, 0, 0}, rs[7] = {0, 0, 0, 0, 0, 0, 0};  // FP32 sums
     auto relax = [&](auto I, P fe) {
@@ -179,7 +248,7 @@ __global__ void __launch_bounds__(TX *TY, sizeof(P) == 4 ? 4 : 2) k_step_12(Step
             if constexpr (D >= 2) rs[cy_of(i) + 3] += d;
         }
         if constexpr (F32 && sr >= 0) dsp[sr] = d;
-        else if (valid) stp<P>(a.f_out, i, N, nodeb, fv[i] + d);
+        else st<P>(a.f_out, i, N, nodeb, fv[i] + d);
     };
     static_for<0, H>([&](auto I) {
         constexpr int i = decltype(I)::value, k = Q - 1 - i;
@@ -204,38 +273,80 @@ __global__ void __launch_bounds__(TX *TY, sizeof(P) == 4 ? 4 : 2) k_step_12(Step
             }
         }
         const double mm = M.m1[0] * M.m1[0] + (D >= 2 ? M.m1[1] * M.m1[1] : 0.0);
-        const double t2 = a.omega * (mm / rho + D * rho * T / (kR * kR) - M.e2);
+        const double t2 = a.omega * (mm * inv + D * rho * T * kInvR2 - M.e2);
         const double R1[3] = {-S1[0], -S1[1], 0.0};
         const Eps ep = eps_from_defects<D>(-S0, R1, t2 - S2);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int sr = special_rank<D>(i);
-            if constexpr (sr >= 0)
-                if (valid) stp<P>(a.f_out, i, N, nodeb, fv[i] + (dsp[sr] + (P)ep.e[sr]));
+            if constexpr (sr >= 0) st<P>(a.f_out, i, N, nodeb, fv[i] + (dsp[sr] + (P)ep.e[sr]));
         });
     }
 
-    // 4. Rotational populations: upwind advection with u (cached stencil
-    //    loads), relaxation to g^eq(T).
-    const GeqCoef<P> gc = geq_coef<P>((P)T);
-    const P nu0 = up[0] * P(1.0 / kR), nu1 = up[1] * P(1.0 / kR);
-    uint32_t gxo[5], gyo[5];
+    // 4. Rotational populations: upwind advection with u, relaxation to
+    //    g^eq(T).
+    {
+        const GeqCoef<P> gc = geq_coef<P>((P)T);
+        const P nu0 = up[0] * P(1.0 / kR), nu1 = up[1] * P(1.0 / kR);
+        P adv[7];
+        P xdp[7], xdm[7], ydp[7], ydm[7];
+        if (fast) {
+            if constexpr (D >= 2) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        gxo[k] = ((uint32_t)nb_coord(xc, k - 2, a.n0, a.open0) + (uint32_t)a.n0 * (uint32_t)yc) * SZ;
-        gyo[k] = D >= 2 ? ((uint32_t)xc + (uint32_t)a.n0 * (uint32_t)nb_coord(yc, k - 2, a.n1, a.open1)) * SZ
-                        : 0u;
-    }
-    P adv[7];
+                for (int j = 0; j < 7; ++j) {
+                    const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.g_in, j, N, SZ);
+                    upwind_diff<P>(ld_buf<P, 0>(r, vb + 3 * SZ, rowo[1]), ld_buf<P, 0>(r, vb + 3 * SZ, rowo[2]),
+                                   gv[j], ld_buf<P, 0>(r, vb + 3 * SZ, rowo[4]),
+                                   ld_buf<P, 0>(r, vb + 3 * SZ, rowo[5]), ydp[j], ydm[j]);
+                }
+            }
+            if constexpr (XDPP) {
+                const uint32_t wb = __builtin_amdgcn_readfirstlane(nodeb);  // lane 0's node
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-        adv[j] = upwind3<P>(nu0, ldp<P>(a.g_in, j, N, gxo[0]), ldp<P>(a.g_in, j, N, gxo[1]), gv[j],
-                            ldp<P>(a.g_in, j, N, gxo[3]), ldp<P>(a.g_in, j, N, gxo[4]));
-        if constexpr (D >= 2)
-            adv[j] += upwind3<P>(nu1, ldp<P>(a.g_in, j, N, gyo[0]), ldp<P>(a.g_in, j, N, gyo[1]), gv[j],
-                                 ldp<P>(a.g_in, j, N, gyo[3]), ldp<P>(a.g_in, j, N, gyo[4]));
+                for (int j = 0; j < 7; ++j) {
+                    const P *gj = reinterpret_cast<const P *>(gin + j * PS + wb);
+                    const P hm1 = wave_shift<kWaveShr1>(gj[-1], gv[j]);
+                    const P hm2 = wave_shift<kWaveShr1>(gj[-2], hm1);
+                    const P hp1 = wave_shift<kWaveShl1>(gj[64], gv[j]);
+                    const P hp2 = wave_shift<kWaveShl1>(gj[65], hp1);
+                    upwind_diff<P>(hm2, hm1, gv[j], hp1, hp2, xdp[j], xdm[j]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 7; ++j) {
+                    const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.g_in, j, N, SZ);
+                    const uint32_t r3 = D >= 2 ? rowo[3] : 0u;
+                    upwind_diff<P>(ld_buf<P, 0>(r, vb + 1 * SZ, r3), ld_buf<P, 0>(r, vb + 2 * SZ, r3), gv[j],
+                                   ld_buf<P, 0>(r, vb + 4 * SZ, r3), ld_buf<P, 0>(r, vb + 5 * SZ, r3),
+                                   xdp[j], xdm[j]);
+                }
+            }
+        } else {
+            uint32_t gxo[5], gyo[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                gxo[k] = ((uint32_t)nb_coord(xc, k - 2, a.n0, a.open0) + (uint32_t)a.n0 * (uint32_t)yc) * SZ;
+                gyo[k] = D >= 2 ? ((uint32_t)xc + (uint32_t)a.n0 * (uint32_t)nb_coord(yc, k - 2, a.n1, a.open1)) * SZ
+                                : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 7; ++j) {
+                const char *gj = gin + j * PS;
+                upwind_diff<P>(ld<P>(gj, gxo[0]), ld<P>(gj, gxo[1]), gv[j], ld<P>(gj, gxo[3]),
+                               ld<P>(gj, gxo[4]), xdp[j], xdm[j]);
+                if constexpr (D >= 2)
+                    upwind_diff<P>(ld<P>(gj, gyo[0]), ld<P>(gj, gyo[1]), gv[j], ld<P>(gj, gyo[3]),
+                                   ld<P>(gj, gyo[4]), ydp[j], ydm[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            adv[j] = upwind_apply<P>(nu0, xdp[j], xdm[j]);
+            if constexpr (D >= 2) adv[j] += upwind_apply<P>(nu1, ydp[j], ydm[j]);
+        }
+        rot_relax_store<P>(gv, adv, gc, om, a.omega, T, M.er, a.g_out, N, nodeb);
     }
-    rot_relax_store<P>(gv, adv, gc, om, a.omega, T, M.er, valid, a.g_out, N, nodeb);
+
 }
 
 // ---------------------------------------------------------------------------
@@ -264,7 +375,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
     static_for<LO, HI>([&](auto I) {
         constexpr int i = decltype(I)::value;
         const uint32_t idx = (uint32_t)(sx[cx_of(i) + 3] + sy[cy_of(i) + 3] + sz[cz_of(i) + 3]);
-        const P f = pop<P>(a.f_in, i, N)[idx];
+        const P f = ldp_stream<P>(a.f_in, i, N, idx * (uint32_t)sizeof(P));
         fv[i - LO] = f;
         const double v = (double)f;
         m0 += v;
@@ -297,7 +408,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
     M.e2 = part[0][lane][4] + part[1][lane][4] + part[2][lane][4] + part[3][lane][4];
     M.er = part[0][lane][5] + part[1][lane][5] + part[2][lane][5] + part[3][lane][5];
     double rho, u[3], T, Etot;
-    finish_moments<3>(M, a.n_rot, rho, u, T, Etot);
+    const double inv = finish_moments<3>(M, a.n_rot, rho, u, T, Etot);
 
     if constexpr (W == 0) {
         if (a.partials) {  // one wave holds all 64 nodes of the tile
@@ -318,7 +429,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
     const P om = (P)a.omega;
 
     // Rotational advection for the wave's j's: 3-D upwind stencil from global.
-    const P nu[3] = {up[0] / P(kR), up[1] / P(kR), up[2] / P(kR)};
+    const P nu[3] = {up[0] * P(1.0 / kR), up[1] * P(1.0 / kR), up[2] * P(1.0 / kR)};
     const uint32_t sxy = (uint32_t)a.n0 * (uint32_t)a.n1;
     auto advect = [&](auto JJ, P gcen) -> P {
         constexpr int j = decltype(JJ)::value;
@@ -361,7 +472,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
             if constexpr (c2_of<3>(i) != 0) s2 += P(c2_of<3>(i)) * d;
         }
         if constexpr (F32 && sr >= 0) dsp[sr] = d;
-        else if (valid) pop_w<P>(a.f_out, i, N)[node] = fv[i - LO] + d;
+        else if (valid) stp_stream<P>(a.f_out, i, N, node * (uint32_t)sizeof(P), fv[i - LO] + d);
     });
     P gal = P(0), gga = P(0);
     if constexpr (F32) {
@@ -388,17 +499,17 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
         for (int k = 0; k < 8; ++k)
             S[k] = part2[0][lane][k] + part2[1][lane][k] + part2[2][lane][k] + part2[3][lane][k];
         const double mm = M.m1[0] * M.m1[0] + M.m1[1] * M.m1[1] + M.m1[2] * M.m1[2];
-        const double t2 = a.omega * (mm / rho + 3.0 * rho * T / (kR * kR) - M.e2);
+        const double t2 = a.omega * (mm * inv + 3.0 * rho * T * kInvR2 - M.e2);
         const double R1[3] = {-S[1], -S[2], -S[3]};
         const Eps ep = eps_from_defects<3>(-S[0], R1, t2 - S[4]);
         static_for<LO, HI>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int sr = special_rank<3>(i);
             if constexpr (sr >= 0)
-                if (valid) pop_w<P>(a.f_out, i, N)[node] = fv[i - LO] + (dsp[sr] + (P)ep.e[sr]);
+                if (valid) stp_stream<P>(a.f_out, i, N, node * (uint32_t)sizeof(P), fv[i - LO] + (dsp[sr] + (P)ep.e[sr]));
         });
         double ga_d, ga_g;
-        gfix_from_defects(a.omega * (1.0 - S[7]) - S[5], a.omega * (T / (kR * kR) - M.er) - S[6],
+        gfix_from_defects(a.omega * (1.0 - S[7]) - S[5], a.omega * (T * kInvR2 - M.er) - S[6],
                           ga_d, ga_g);
         gal = (P)ga_d;
         gga = (P)ga_g;
@@ -410,7 +521,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
         if constexpr (F32)
             gn = gcen - adv + (rl + P(kW1[iabs(j - 3)]) * (gal + P((j - 3) * (j - 3)) * gga));
         else gn = gcen - adv + rl;
-        if (valid) pop_w<P>(a.g_out, j, N)[node] = gn;
+        if (valid) stp_stream<P>(a.g_out, j, N, node * (uint32_t)sizeof(P), gn);
     };
     relax_store(Int<J0>{}, g0, adv0);
     if constexpr (HAS1) relax_store(Int<J1 < 7 ? J1 : 0>{}, g1, adv1);

@@ -63,6 +63,26 @@ def test_2d_fp64(torch_cuda, shape, bc, n_rot):
     assert rel_err(g["tot"], o["tot"]) <= FP64_TOL
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("bc", [["periodic", "periodic"], ["open", "periodic"]])
+def test_2d_interior_and_edge_waves(torch_cuda, dtype, bc):
+    """200 x 40 with the default 256 x 1 tile: waves over x = 64..127 and
+    128..191 lie inside the grid (immediate-offset path, lane shifts for the
+    rotational stencil in FP32), the others touch an edge or the ragged tail
+    (per-lane wrap/clamp path)."""
+    shape = (200, 40)
+    announce(f"2-D {dtype} {shape} {bc}")
+    fields = smooth_fields(shape, 7)
+    dt = getattr(torch_cuda, dtype)
+    g = gpu_run(shape, bc, 3.0, 0.85, dt, fields, 20, perturb_seed=5)
+    o = oracle_run(shape, bc, 3.0, 0.85, fields, 20, perturb_seed=5)
+    if dtype == "float64":
+        _fields_check(g, o, FP64_TOL, "rel")
+        assert rel_err(g["f"], o["f"]) <= FP64_TOL and rel_err(g["g"], o["g"]) <= FP64_TOL
+    else:
+        _fields_check(g, o, FP32_TOL, "abs")
+
+
 def test_2d_fp32_vs_fp64_oracle(torch_cuda):
     """FP32 populations with FP64 moments/T: error against the FP64 oracle
     after 100 steps of the 2-D periodic recipe at 128^2."""
@@ -93,11 +113,14 @@ def test_3d(torch_cuda, shape, bc, dtype):
 
 
 @pytest.mark.parametrize("dim,tiles", [(1, [(64, 1, 1), (512, 1, 1), (1024, 1, 1)]),
-                                       (2, [(32, 8, 1), (128, 2, 1), (16, 16, 1), (64, 8, 1)]),
+                                       (2, [(32, 8, 1), (128, 2, 1), (16, 16, 1), (64, 8, 1), (64, 4, 1),
+                                            (64, 2, 1), (32, 16, 1)]),
                                        (3, [(32, 2, 1), (16, 4, 1)])])
 def test_tile_shapes_bitwise_identical(torch_cuda, dim, tiles):
-    """No cross-node arithmetic in a step: every tile shape gives the same bits."""
-    shape = {1: (777,), 2: (90, 70), 3: (40, 9, 5)}[dim]
+    """No cross-node arithmetic in a step: every tile shape gives the same bits
+    (the 2-D grid has interior waves for every tile width, so the
+    immediate-offset and the per-lane wrap paths are both compared)."""
+    shape = {1: (777,), 2: (200, 40), 3: (40, 9, 5)}[dim]
     bc = ["periodic"] * dim
     fields = smooth_fields(shape, 8)
     announce(f"tiles dim={dim}")
