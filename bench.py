@@ -172,7 +172,8 @@ def extra_batch(seed=0):
     return out
 
 
-def extra_surrogate(train_candidates=2048, test_candidates=2048, train_steps=800, calls=16):
+def extra_surrogate(train_candidates=8192, test_candidates=2048, train_steps=3000, calls=16,
+                    pairs_per_tube=16, train_batch=32, lr=2e-3):
     """Learned surrogate vs plain LBM on held-out 4096-node tubes: 16 calls
     of k = 16 steps (256 steps) with the admission check and plain-LBM
     fallback; errors judged against the plain LBM run (Sec. VI relative L1)."""
@@ -183,10 +184,10 @@ def extra_surrogate(train_candidates=2048, test_candidates=2048, train_steps=800
     from paper_1606_06107_amd import surrogate as SG
     t0 = time.perf_counter()
     bt = SG.stable_tubes(train_candidates, seed=0)
-    x, tg, gm = SG.make_pairs(bt, pairs_per_tube=8, seed=1)
-    sur = Surrogate(32, 4096)
+    x, tg, gm = SG.make_pairs(bt, pairs_per_tube=pairs_per_tube, seed=1)
+    sur = Surrogate(train_batch, 4096)
     sur.set_params(SG.init_params(0))
-    hist = SG.train(sur, x, tg, gm, steps=train_steps, lr=2e-3, log_every=train_steps // 4)
+    hist = SG.train(sur, x, tg, gm, steps=train_steps, lr=lr, log_every=train_steps // 4)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del x, tg
@@ -221,15 +222,23 @@ def extra_surrogate(train_candidates=2048, test_candidates=2048, train_steps=800
     err, err_id = l1(xr, ref), l1(x0, ref)
     xn, _ = SG.rollout(surB, x0, gamma, fb, calls, fallback=False)
     err_nf = l1(xn, ref)
+    # one call (16 steps) from the initial fields against 16 plain steps
+    one = Batch(te.lengths, te.n_rot, te.tau, np.full(B, 16), dtype=torch.float32)
+    one.init(te.rho, te.u[0], te.T).step()
+    err_one = l1(surB.forward(x0, gamma), SG.fields_of(one))
+    err_one_id = l1(x0, SG.fields_of(one))
     accepted = int(acc.sum().item())
     return {"workload": f"{B} held-out stable 4096-node tubes, {calls} calls x 16 steps",
-            "train": {"stable_tubes": int(bt.num), "pairs": int(bt.num * 8), "adam_steps": train_steps,
+            "train": {"stable_tubes": int(bt.num), "pairs": int(bt.num * pairs_per_tube),
+                      "batch": train_batch, "adam_steps": train_steps,
                       "seconds": round(t_train, 2), "loss": hist},
             "t_lbm_ms": round(t_lbm, 3), "t_surrogate_with_fallback_ms": round(t_sur, 3),
             "speedup": round(t_lbm / t_sur, 3), "accepted_fraction": round(accepted / (B * calls), 4),
             "rel_l1_rho_u_T": [round(float(v), 5) for v in err],
             "rel_l1_no_fallback": [round(float(v), 5) for v in err_nf],
-            "rel_l1_identity": [round(float(v), 5) for v in err_id]}
+            "rel_l1_identity": [round(float(v), 5) for v in err_id],
+            "one_call_rel_l1": [round(float(v), 5) for v in err_one],
+            "one_call_rel_l1_identity": [round(float(v), 5) for v in err_one_id]}
 
 
 def main():

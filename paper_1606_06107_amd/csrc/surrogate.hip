@@ -39,11 +39,21 @@ constexpr int B_KC = 0, B_BC = 320, B_W1 = 384, B_B1 = 8576, B_W2 = 8704, B_B2 =
 constexpr int P_WH = P_BLK + NB * BLK, P_BH = P_WH + FOUT * C, NPARAMS = P_BH + FOUT;
 static_assert(NPARAMS == LBM_SUR_NPARAMS, "parameter count");
 // BF16 copies (element offsets)
-constexpr int Q_WE = 0, Q_BLK = 1024, QBLK = 32768;  // per block: W1, W1t, W2, W2t
-constexpr int Q_W1 = 0, Q_W1T = 8192, Q_W2 = 16384, Q_W2T = 24576;
+constexpr int Q_WE = 0, Q_BLK = 1024, QBLK = 40960;  // per block: W1, W1t, W2, W2t, W2p
+constexpr int Q_W1 = 0, Q_W1T = 8192, Q_W2 = 16384, Q_W2T = 24576, Q_W2P = 32768;
 constexpr int Q_WHP = Q_BLK + NB * QBLK;   // [32][64], rows >= 12 zero
 constexpr int Q_WHTP = Q_WHP + 32 * C;     // [64][16], cols >= 12 zero
 constexpr int QTOTAL = Q_WHTP + C * 16;
+
+// Fragment order of the second MLP product in the fused forward kernel: the
+// output of the first product (hidden x tokens) leaves lane half h holding,
+// within each 16-wide hidden chunk, offsets {4h..4h+3, 8+4h..8+4h+3}; used
+// directly as the A operand, its k slot 8h + e therefore means hidden offset
+// 4h + e (+4 for e >= 4).  W2p stores W2 with its hidden index in that order.
+__host__ __device__ constexpr int w2p_hidden(int kk) {
+    const int q = kk / 16, s = kk % 16, h = s / 8, e = s % 8;
+    return 16 * q + 4 * h + e + (e >= 4 ? 4 : 0);
+}
 
 // Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
 __device__ __forceinline__ __bf16 to_bf16(float f) {
@@ -366,8 +376,10 @@ __global__ void __launch_bounds__(256) k_pack(const float *P, __bf16 *Q) {
         else if (r < Q_W2) { const int i = r - Q_W1T, k = i / HID, n = i % HID;  // W1t [64][128]
             v = blk[B_W1 + n * C + k]; }
         else if (r < Q_W2T) v = blk[B_W2 + (r - Q_W2)];                          // W2 [64][128]
-        else { const int i = r - Q_W2T, k = i / C, n = i % C;                    // W2t [128][64]
+        else if (r < Q_W2P) { const int i = r - Q_W2T, k = i / C, n = i % C;     // W2t [128][64]
             v = blk[B_W2 + n * HID + k]; }
+        else { const int i = r - Q_W2P, n = i / HID, kk = i % HID;               // W2p [64][128]
+            v = blk[B_W2 + n * HID + w2p_hidden(kk)]; }
     } else if (e < Q_WHTP) {
         const int i = e - Q_WHP, n = i / C, k = i % C;                           // Whp [32][64]
         v = n < FOUT ? P[P_WH + n * C + k] : 0.0f;
@@ -389,6 +401,195 @@ __global__ void __launch_bounds__(256) k_adam(int n, float *p, float *m, float *
     m[e] = mm;
     v[e] = vv;
     p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference: one workgroup (4 waves) carries a tile of 128 consecutive
+// tokens of one tube through the embedding, the four blocks and the head,
+// with the residual stream in LDS (FP32) and the convolution output in LDS
+// (BF16).  Each block's depthwise convolution needs two tokens on each side,
+// so the tile carries 8 halo tokens per side and writes the middle 112.
+// Wave w owns rows 32w..32w+31.  The first MLP product is formed transposed,
+// Z1^T = W1 Hc^T, so that each lane's accumulators (one token, 16 hidden
+// units) become, after bias, GELU and BF16 rounding, the A operand of the
+// second product in registers (hidden order as in W2p).  Rounding points
+// are those of the layer-wise kernels: the inputs, Hc, GELU(Z1) and H4.
+// ---------------------------------------------------------------------------
+constexpr int FR = 128;                 // token rows per tile
+constexpr int FHALO = 2 * NB;           // halo rows per side
+constexpr int FOUTR = FR - 2 * FHALO;   // output rows per tile
+constexpr int HS = C + 4;               // FP32 row stride in LDS
+constexpr int BS = C + 8;               // BF16 row stride in LDS
+
+struct FwdArgs {
+    int B, L, T, ntile;
+    const double *x, *gamma;
+    const float *P;
+    const __bf16 *Q;
+    double *y;
+};
+
+// GELU (tanh form) as z / (1 + exp(-2a)), a = sqrt(2/pi) (z + 0.044715 z^3),
+// which equals 0.5 z (1 + tanh a); hardware exp2 and reciprocal.
+__device__ __forceinline__ float gelu_fast(float z) {
+    constexpr float c0 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) log2(e)
+    constexpr float c1 = c0 * 0.044715f;
+    const float e = __builtin_amdgcn_exp2f(z * fmaf(c1, z * z, c0));
+    return z * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+__device__ __forceinline__ bf16x8 ld_frag(const __bf16 *p) {
+    return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+__global__ void __launch_bounds__(256) k_fwd_fused(FwdArgs a) {
+    __shared__ __attribute__((aligned(16))) float Hf[FR * HS];
+    __shared__ __attribute__((aligned(16))) __bf16 Hb[FR * BS];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, n32 = l & 31, hl = l >> 5;
+    const int b = blockIdx.x / a.ntile, tile = blockIdx.x % a.ntile;
+    const int t0 = tile * FOUTR - FHALO;  // token of row 0
+    const int r0 = 32 * w;
+    const size_t BL = (size_t)a.B * a.L;
+    auto in_tube = [&](int r) { return t0 + r >= 0 && t0 + r < a.T; };
+
+    // Embedding H0 = X We^T + be; rows outside the tube are zero (padding).
+    {
+        bf16x8 xa;
+        const int t = t0 + r0 + n32;
+        const bool in = t >= 0 && t < a.T;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int p = 2 * hl + e / 4, c = e % 4;
+            double v = 0.0;
+            if (in) v = c < 3 ? a.x[(size_t)c * BL + (size_t)b * a.L + 4 * t + p] : a.gamma[b];
+            xa[e] = (__bf16)(float)((v - kMu[c]) / kSd[c]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int ch = 32 * ct + n32;
+            f32x16 acc;
+            for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, ld_frag(a.Q + Q_WE + ch * FIN + 8 * hl), acc, 0, 0, 0);
+            const float be = a.P[P_BE + ch];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
+                Hf[r * HS + ch] = in_tube(r) ? acc[i] + be : 0.0f;
+            }
+        }
+    }
+
+    for (int k = 0; k < NB; ++k) {
+        const float *blk = a.P + P_BLK + k * BLK;
+        const __bf16 *qb = a.Q + Q_BLK + k * QBLK;
+        __syncthreads();  // H of every row written
+        // Depthwise convolution: lane = channel, the wave's 32 rows.
+        float hc[32];
+        {
+            const int c = l;
+            float kc[TAPS];
+#pragma unroll
+            for (int q = 0; q < TAPS; ++q) kc[q] = blk[B_KC + c * TAPS + q];
+            const float bc = blk[B_BC + c];
+            float win[36];
+#pragma unroll
+            for (int m = 0; m < 36; ++m) {
+                const int r = r0 + m - 2;
+                win[m] = (r >= 0 && r < FR) ? Hf[r * HS + c] : 0.0f;
+            }
+#pragma unroll
+            for (int m = 0; m < 32; ++m) {
+                float v = win[m + 2] + bc;
+#pragma unroll
+                for (int q = 0; q < TAPS; ++q) v += kc[q] * win[m + q];
+                hc[m] = v;
+            }
+        }
+        __syncthreads();  // every read of H done
+#pragma unroll
+        for (int m = 0; m < 32; ++m) {
+            Hf[(r0 + m) * HS + l] = hc[m];
+            Hb[(r0 + m) * BS + l] = (__bf16)hc[m];
+        }
+        // MLP on the wave's rows.
+        bf16x8 hb[4];  // B operand of Z1^T: token n32, channels 16 s + 8 hl ..
+#pragma unroll
+        for (int s = 0; s < 4; ++s) hb[s] = ld_frag(&Hb[(r0 + n32) * BS + 16 * s + 8 * hl]);
+        f32x16 acc2[2];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+            for (int i = 0; i < 16; ++i) acc2[ot][i] = 0.0f;
+#pragma unroll
+        for (int hp = 0; hp < 2; ++hp) {  // pairs of 32-wide hidden tiles
+            f32x16 acc1[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int h = 2 * hp + u;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    acc1[u][i] = blk[B_B1 + 32 * h + 8 * (i >> 2) + 4 * hl + (i & 3)];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int h = 2 * hp + u;
+                    acc1[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        ld_frag(qb + Q_W1 + (32 * h + n32) * C + 16 * s + 8 * hl), hb[s], acc1[u], 0, 0, 0);
+                }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int h = 2 * hp + u;
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    bf16x8 af;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) af[e] = (__bf16)gelu_fast(acc1[u][8 * cc + e]);
+                    const int q = 2 * h + cc;  // 16-wide hidden chunk
+#pragma unroll
+                    for (int ot = 0; ot < 2; ++ot)
+                        acc2[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            af, ld_frag(qb + Q_W2P + (32 * ot + n32) * HID + 16 * q + 8 * hl), acc2[ot], 0, 0, 0);
+                }
+            }
+        }
+        // H' = Hc + A1 W2^T + b2 on the wave's rows (zero outside the tube).
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) {
+            const int ch = 32 * ot + n32;
+            const float b2 = blk[B_B2 + ch];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
+                const float v = Hf[r * HS + ch] + acc2[ot][i] + b2;
+                Hf[r * HS + ch] = in_tube(r) ? v : 0.0f;
+            }
+        }
+    }
+
+    // Head: Y = bf16(H4) Wh^T + bh on the wave's rows; y = x + 0.1 Y.
+    f32x16 acc;
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const float *hr = &Hf[(r0 + n32) * HS + 16 * s + 8 * hl];
+        bf16x8 ha;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ha[e] = (__bf16)hr[e];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha, ld_frag(a.Q + Q_WHP + n32 * C + 16 * s + 8 * hl), acc, 0,
+                                                      0, 0);
+    }
+    if (n32 < FOUT) {
+        const int p = n32 / 3, c = n32 % 3;
+        const float bh = a.P[P_BH + n32];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
+            if (r < FHALO || r >= FR - FHALO || !in_tube(r)) continue;
+            const size_t idx = (size_t)c * BL + (size_t)b * a.L + 4 * (t0 + r) + p;
+            a.y[idx] = a.x[idx] + OUT_SCALE * (double)(acc[i] + bh);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -623,11 +824,9 @@ lbm_status lbm_sur_forward(const lbm_sur_desc *d, const double *x, const double 
         return sfail(LBM_EINVAL, "NULL argument");
     if (x == y) return sfail(LBM_EINVAL, "y may not alias x");
     hipStream_t s = (hipStream_t)stream;
-    size_t bytes;
-    const Bufs b = carve(d, &bytes);
-    forward(d, b, x, gamma, s);
-    const Shape sh{d->batch, d->length, d->length / PATCH, d->batch * d->length / PATCH};
-    hipLaunchKernelGGL(k_head_out, dim3(nblk((size_t)3 * d->batch * d->length)), dim3(256), 0, s, sh, x, b.Y, y);
+    const int T = d->length / PATCH, ntile = (T + FOUTR - 1) / FOUTR;
+    FwdArgs fa{d->batch, d->length, T, ntile, x, gamma, d->params, (const __bf16 *)d->params_bf16, y};
+    hipLaunchKernelGGL(k_fwd_fused, dim3((unsigned)(d->batch * ntile)), dim3(256), 0, s, fa);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
 }
