@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # WRITE_SIZE, scaled by the same counters on a plain device copy of known
 # size (profiles/k_step_12_d2q49_1024x1024_fp32.md), valid only for the
 # kernel sources they were taken on (sha256 of the files below).
-TRAFFIC = {"bytes": 491_475_866, "nodes": 1024 * 1024, "tile": (256, 1),
-           "sha256": "4691d32227bf5e871542f7f10ab3be01fb64a9bf472e841c1a8184e4764b8771"}
+TRAFFIC = {"bytes": 479_095_366, "nodes": 1024 * 1024, "tile": (256, 1),
+           "sha256": "278d32782a6e3cbcaa99c737b0dc69d229f94567b1519a2dc96e183516a9a117"}
 TRAFFIC_SOURCES = ("paper_1606_06107_amd/csrc/step_impl.hpp",
                    "paper_1606_06107_amd/csrc/lbm_device.hpp",
                    "paper_1606_06107_amd/csrc/step_12_f32.hip")
