@@ -3,6 +3,9 @@
 Every .hip file is compiled to an object in parallel, then linked into one
 shared library beside this file.  Packed-FP32 instructions are disabled
 (-packed-fp32-ops): the compiler emits scalar FP32 arithmetic instead.
+Multiply-adds are fused only within a source expression (-ffp-contract=on),
+so a kernel's rounding does not depend on how the surrounding code is split
+into basic blocks (launch shapes and streaming schemes give identical bits).
 """
 from __future__ import annotations
 
@@ -19,7 +22,7 @@ LIB = os.path.join(HERE, "liblbmx.so")
 BUILD = os.path.join(ROOT, "_build")
 
 ARCH = "gfx950"
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

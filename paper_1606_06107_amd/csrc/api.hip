@@ -121,8 +121,9 @@ struct lbm_sim_s {
     lbm_desc d;
     hipStream_t stream;    // caller's stream
     hipStream_t capture;   // private stream used only to record graphs
-    int cur = 0;           // buffer index of the current state
-    int streamed = 1;      // f[cur] holds streamed populations (just initialised)
+    int fcur = 0, gcur = 0;               // buffer indices of the current f and g
+    int layout = lbmx::kLayoutStreamed;   // what f[fcur] holds (just initialised)
+    int inplace = 0;                      // translational streaming in one buffer
     int64_t t = 0;
     int tile[3];
     int graphs = 1;
@@ -131,7 +132,7 @@ struct lbm_sim_s {
     int64_t mon_cap = 0;
     struct Entry {
         int64_t n, t0, every;
-        int cur, streamed, tile0, tile1;
+        int fcur, gcur, layout, inplace, tile0, tile1;
         double *series;
         hipGraphExec_t exec;
     };
@@ -147,14 +148,28 @@ void clear_cache(lbm_sim s) {
 
 int64_t N_of(const lbm_desc &d) { return d.n[0] * d.n[1] * d.n[2]; }
 
+// Host-side state after n more steps (the time counter aside).
+void advance(lbm_sim s, int64_t n) {
+    if (n <= 0) return;
+    s->gcur = (int)((s->gcur + n) & 1);
+    if (s->inplace) {
+        // even steps turn kLayoutStreamed into kLayoutSwapped, odd steps back
+        if (n & 1)
+            s->layout = s->layout == lbmx::kLayoutStreamed ? lbmx::kLayoutSwapped : lbmx::kLayoutStreamed;
+    } else {
+        s->fcur = (int)((s->fcur + n) & 1);
+        s->layout = lbmx::kLayoutPost;
+    }
+}
+
 // Enqueue one time step on stream st and advance the host-side state.
 hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
     const lbm_desc &d = s->d;
     lbmx::StepArgs a;
-    a.f_in = d.f[s->cur];
-    a.g_in = d.g[s->cur];
-    a.f_out = d.f[s->cur ^ 1];
-    a.g_out = d.g[s->cur ^ 1];
+    a.f_in = d.f[s->fcur];
+    a.g_in = d.g[s->gcur];
+    a.f_out = s->inplace ? d.f[s->fcur] : d.f[s->fcur ^ 1];
+    a.g_out = d.g[s->gcur ^ 1];
     a.n0 = (int)d.n[0];
     a.n1 = (int)d.n[1];
     a.n2 = (int)d.n[2];
@@ -162,7 +177,10 @@ hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
     a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
     a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
     a.N = (uint32_t)N_of(d);
-    a.streamed = s->streamed;
+    a.layout = s->layout;
+    a.scheme = !s->inplace ? lbmx::kSchemePingPong
+                           : (s->layout == lbmx::kLayoutStreamed ? lbmx::kSchemeInPlaceEven
+                                                                 : lbmx::kSchemeInPlaceOdd);
     a.omega = 1.0 / d.tau;
     a.n_rot = d.n_rot;
     a.ntiles = lbmx::step_ntiles(d.dim, s->tile, a.n0, a.n1, a.n2, &a.tiles0, &a.tiles1, &a.tiles2);
@@ -177,10 +195,18 @@ hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
                                 s->mon_series + (s->t / s->mon_every) * K, st);
         if (e != hipSuccess) return e;
     }
-    s->cur ^= 1;
-    s->streamed = 0;
+    advance(s, 1);
     s->t += 1;
     return hipSuccess;
+}
+
+// In-place streaming needs a bijective scatter x -> x + c: every axis
+// periodic; 1-D and 2-D lattices.
+bool inplace_possible(const lbm_desc &d) {
+    if (d.dim > 2) return false;
+    for (int a = 0; a < d.dim; ++a)
+        if (d.bc[a] != LBM_BC_PERIODIC) return false;
+    return true;
 }
 
 lbm_status make_sim(const lbm_desc *desc, void *stream, lbm_sim *out) {
@@ -194,6 +220,7 @@ lbm_status make_sim(const lbm_desc *desc, void *stream, lbm_sim *out) {
     s->d = *desc;
     s->stream = (hipStream_t)stream;
     default_tile(desc->dim, s->tile);
+    s->inplace = inplace_possible(*desc) ? 1 : 0;
     if (hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess) {
         delete s;
         return fail(LBM_EDEVICE, "hipStreamCreateWithFlags failed");
@@ -265,27 +292,28 @@ lbm_status lbm_step(lbm_sim s, int64_t nsteps) {
     const bool mon = s->mon_every > 0;
     const int64_t t0key = mon ? s->t : -1;
     for (auto &en : s->cache) {
-        if (en.n == nsteps && en.cur == s->cur && en.streamed == s->streamed && en.t0 == t0key &&
+        if (en.n == nsteps && en.fcur == s->fcur && en.gcur == s->gcur && en.layout == s->layout &&
+            en.inplace == s->inplace && en.t0 == t0key &&
             en.tile0 == s->tile[0] && en.tile1 == s->tile[1] && en.every == s->mon_every &&
             en.series == s->mon_series) {
             hipError_t e = hipGraphLaunch(en.exec, s->stream);
             if (e != hipSuccess) return hip_fail(e, "graph launch");
-            s->cur = (int)((s->cur + nsteps) & 1);
-            s->streamed = 0;
+            advance(s, nsteps);
             s->t += nsteps;
             return LBM_OK;
         }
     }
     // Record nsteps launches on the private stream and replay them as one graph.
-    const int cur0 = s->cur, str0 = s->streamed;
+    const int fcur0 = s->fcur, gcur0 = s->gcur, lay0 = s->layout;
     const int64_t t0 = s->t;
     hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin capture");
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue_step(s, s->capture);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->capture, &graph);
-    s->cur = cur0;
-    s->streamed = str0;
+    s->fcur = fcur0;
+    s->gcur = gcur0;
+    s->layout = lay0;
     s->t = t0;
     if (e != hipSuccess || e2 != hipSuccess) {
         if (graph) hipGraphDestroy(graph);
@@ -299,12 +327,11 @@ lbm_status lbm_step(lbm_sim s, int64_t nsteps) {
         hipGraphExecDestroy(s->cache.front().exec);
         s->cache.erase(s->cache.begin());
     }
-    s->cache.push_back({nsteps, t0key, s->mon_every, cur0, str0, s->tile[0], s->tile[1],
-                        s->mon_series, exec});
+    s->cache.push_back({nsteps, t0key, s->mon_every, fcur0, gcur0, lay0, s->inplace, s->tile[0],
+                        s->tile[1], s->mon_series, exec});
     e = hipGraphLaunch(exec, s->stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
-    s->cur = (int)((cur0 + nsteps) & 1);
-    s->streamed = 0;
+    advance(s, nsteps);
     s->t = t0 + nsteps;
     return LBM_OK;
 }
@@ -313,8 +340,8 @@ lbm_status lbm_moments(lbm_sim s, double *rho, double *u, double *T, double *tot
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     const lbm_desc &d = s->d;
     lbmx::FieldArgs a = {};
-    a.f = d.f[s->cur];
-    a.g = d.g[s->cur];
+    a.f = d.f[s->fcur];
+    a.g = d.g[s->gcur];
     a.n0 = (int)d.n[0];
     a.n1 = (int)d.n[1];
     a.n2 = (int)d.n[2];
@@ -322,7 +349,7 @@ lbm_status lbm_moments(lbm_sim s, double *rho, double *u, double *T, double *tot
     a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
     a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
     a.N = (uint32_t)N_of(d);
-    a.streamed = s->streamed;
+    a.layout = s->layout;
     a.n_rot = d.n_rot;
     a.rho = rho;
     a.u = u;
@@ -348,8 +375,8 @@ lbm_status lbm_populations(lbm_sim s, void *f_out, void *g_out) {
             (g_out && (g_out == d.f[k] || g_out == d.g[k])))
             return fail(LBM_EINVAL, "export buffers must differ from the state buffers");
     lbmx::FieldArgs a = {};
-    a.f = d.f[s->cur];
-    a.g = d.g[s->cur];
+    a.f = d.f[s->fcur];
+    a.g = d.g[s->gcur];
     a.n0 = (int)d.n[0];
     a.n1 = (int)d.n[1];
     a.n2 = (int)d.n[2];
@@ -357,7 +384,7 @@ lbm_status lbm_populations(lbm_sim s, void *f_out, void *g_out) {
     a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
     a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
     a.N = (uint32_t)N_of(d);
-    a.streamed = s->streamed;
+    a.layout = s->layout;
     a.f_out = f_out;
     a.g_out = g_out;
     hipError_t e = lbmx::launch_export(d.dtype, d.dim, a, s->stream);
@@ -385,6 +412,17 @@ lbm_status lbm_time(lbm_sim s, int64_t *t) {
 lbm_status lbm_set_graphs(lbm_sim s, int32_t enable) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     s->graphs = enable ? 1 : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_inplace(lbm_sim s, int32_t enable) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (s->t != 0 || s->layout != lbmx::kLayoutStreamed)
+        return fail(LBM_EINVAL, "the streaming scheme can only be chosen before the first step");
+    if (enable && !inplace_possible(s->d))
+        return fail(LBM_EUNSUPPORTED, "in-place streaming needs a 1-D or 2-D grid periodic in every axis");
+    s->inplace = enable ? 1 : 0;
+    clear_cache(s);
     return LBM_OK;
 }
 

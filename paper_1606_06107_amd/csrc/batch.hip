@@ -544,7 +544,7 @@ lbm_status lbm_batch_moments(const lbm_batch_desc *desc, double *rho, double *u,
     a.n1 = 1;
     a.n2 = 1;
     a.N = (uint32_t)desc->total_nodes;
-    a.streamed = 1;  // the batch state is kept streamed
+    a.layout = lbmx::kLayoutStreamed;  // the batch state is kept streamed
     a.n_rot = 0.0;
     a.rho = rho;
     a.u = u;

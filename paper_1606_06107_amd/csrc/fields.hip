@@ -37,7 +37,7 @@ __device__ __forceinline__ void block_totals(double (&v)[K], double *dst) {
 
 // ---------------------------------------------------------------------------
 // Initial state: f = f^eq(rho,u,T), g = g^eq(T), evaluated in FP64, stored
-// streamed.
+// streamed (kLayoutStreamed).
 // ---------------------------------------------------------------------------
 template <typename P, int D> __global__ void __launch_bounds__(256) k_init(InitArgs a) {
     const uint32_t x = blockIdx.x * 256u + threadIdx.x;
@@ -59,6 +59,11 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_init(InitA
 // ---------------------------------------------------------------------------
 // Fields, totals and canonical export (runtime loop over populations).
 // ---------------------------------------------------------------------------
+// Node holding the value of f_i(x, t) for the buffer's layout (its slot is
+// src_slot).
+template <int D> __device__ __forceinline__ int src_slot(const FieldArgs &a, int i) {
+    return a.layout == kLayoutSwapped ? Lat<D>::Q - 1 - i : i;
+}
 template <int D> __device__ __forceinline__ uint32_t src_index(const FieldArgs &a, int x, int y, int z,
                                                               int i, int shift) {
     const int sx = nb_coord(x, -cx_of(i) * shift, a.n0, a.open0);
@@ -72,10 +77,10 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_fields(Fie
     const bool valid = x < a.N;
     const uint32_t xn = valid ? x : a.N - 1;
     const int cx = xn % a.n0, cy = (xn / a.n0) % a.n1, cz = xn / (a.n0 * a.n1);
-    const int shift = 1 - a.streamed;
+    const int shift = a.layout == kLayoutStreamed ? 0 : 1;
     Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
     for (int i = 0; i < Lat<D>::Q; ++i) {
-        const double v = (double)pop<P>(a.f, i, a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
+        const double v = (double)pop<P>(a.f, src_slot<D>(a, i), a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
         M.m0 += v;
         M.m1[0] += cx_of(i) * v;
         if (D >= 2) M.m1[1] += cy_of(i) * v;
@@ -114,10 +119,11 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_export(Fie
     const uint32_t x = blockIdx.x * 256u + threadIdx.x;
     if (x >= a.N) return;
     const int cx = x % a.n0, cy = (x / a.n0) % a.n1, cz = x / (a.n0 * a.n1);
-    const int shift = 1 - a.streamed;
+    const int shift = a.layout == kLayoutStreamed ? 0 : 1;
     if (a.f_out)
         for (int i = 0; i < Lat<D>::Q; ++i)
-            pop_w<P>(a.f_out, i, a.N)[x] = pop<P>(a.f, i, a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
+            pop_w<P>(a.f_out, i, a.N)[x] =
+                pop<P>(a.f, src_slot<D>(a, i), a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
     if (a.g_out)
         for (int j = 0; j < 7; ++j) pop_w<P>(a.g_out, j, a.N)[x] = pop<P>(a.g, j, a.N)[x];
 }

@@ -6,17 +6,31 @@
 
 namespace lbmx {
 
+// What a translational population buffer holds at time t (slot i of node x):
+//   kLayoutPost     f*_i(x, t-1), post-collision: f_i(x, t) = slot i at S(x - c_i)
+//   kLayoutStreamed f_i(x, t) itself (after initialisation; even in-place steps)
+//   kLayoutSwapped  f*_i(x, t-1) kept in the opposite slot: f_i(x, t) = slot
+//                   opp(i) at x - c_i (after an even in-place step)
+enum { kLayoutPost = 0, kLayoutStreamed = 1, kLayoutSwapped = 2 };
+// Step schemes: ping-pong (f_in -> f_out, output kLayoutPost), and the two
+// halves of in-place streaming on periodic grids (f_in == f_out): even
+// (kLayoutStreamed -> kLayoutSwapped: every access local, the result goes to
+// the opposite slot) and odd (kLayoutSwapped -> kLayoutStreamed: gather slot
+// opp(i) from x - c_i, scatter slot i to x + c_i; each node reads and writes
+// the same set of locations, so nodes never conflict).
+enum { kSchemePingPong = 0, kSchemeInPlaceEven = 1, kSchemeInPlaceOdd = 2 };
+
 // Arguments of the per-step kernels (one time step of Sec. V B).
 struct StepArgs {
-    const void *f_in;   // [Q][N] translational populations (see `streamed`)
+    const void *f_in;   // [Q][N] translational populations (see `layout`)
     const void *g_in;   // [7][N] rotational populations at time t
-    void *f_out;        // [Q][N] post-collision translational populations
+    void *f_out;        // [Q][N] translational populations after the step
     void *g_out;        // [7][N] rotational populations at time t+1
     int n0, n1, n2;     // nodes per axis
     int open0, open1, open2;  // 1 = open (clamp), 0 = periodic
     uint32_t N;         // n0*n1*n2
-    int streamed;       // 1: f_in holds streamed populations f(t) (read in place);
-                        // 0: f_in holds post-collision f*(t-1) (gathered from x - c)
+    int layout;         // kLayout* of f_in
+    int scheme;         // kScheme*
     double omega;       // 1/tau
     double n_rot;       // rotational degrees of freedom
     double *partials;   // NULL, or [ntiles][2+D] FP64 per-tile totals of time t
@@ -29,7 +43,7 @@ struct FieldArgs {
     const void *g;
     int n0, n1, n2, open0, open1, open2;
     uint32_t N;
-    int streamed;
+    int layout;         // kLayout* of f
     double n_rot;
     double *rho, *u, *T;  // any may be NULL
     double *partials;     // NULL or [nblocks][2+D]
@@ -54,6 +68,8 @@ void set_error(const char *msg);
 hipError_t launch_step(int dtype, int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_12_f32(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_12_f64(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step_12_f32_inplace(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step_12_f64_inplace(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_3(int dtype, const int tile[3], const StepArgs &a, hipStream_t s);
 
 // Compiled tile shapes (nodes per workgroup along x, y).

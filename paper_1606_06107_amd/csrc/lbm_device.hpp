@@ -253,8 +253,9 @@ __device__ __forceinline__ void feq_pair(const FeqCoef<P> &c, P &fplus, P &fminu
     const P E = p0 + a2 * (p2 + a2 * P(1.0 / 24.0));
     const P O = (p1 + a2 * P(1.0 / 6.0)) * a;
     const P wr = P(w_of<D>(I)) * c.rho;
-    fplus = wr * (E + O);
-    fminus = wr * (E - O);
+    const P wE = wr * E;
+    fplus = wE + wr * O;
+    fminus = wE - wr * O;
 }
 
 // ---------------------------------------------------------------------------

@@ -5,15 +5,20 @@
 //   gather the streamed f(x, t) = f*(S(x - c_i), t-1)   (pull; S = wrap/clamp)
 //   FP64 moments rho, rho u, E_t, e_r and the temperature T   (steps 3-4)
 //   fourth-order Hermite equilibria f^eq(rho,u,T), g^eq(T)     (Sec. IV)
-//   BGK relaxation of f; the post-collision f*(x, t) is stored in place of x
+//   BGK relaxation of f and its storage (below)
 //   forward-Euler third-order-upwind advection of g with u, plus relaxation
 //   (Sec. V A), g(x, t+1) stored
 //   optional per-tile FP64 totals of time t (mass, momentum, energy)
-// Populations are SoA [Q][N], node index x fastest.  Right after
-// initialisation f is stored streamed (`streamed` = 1, read in place).
+// Populations are SoA [Q][N], node index x fastest.  Translational storage
+// (kScheme* / kLayout* in launch.hpp): ping-pong (pull from f_in, the
+// post-collision f*(x, t) stored at x in f_out) or, on grids periodic in
+// every axis, in place in one buffer (even/odd steps).  The rotational
+// populations always ping-pong.
 //
-// Populations go through the streaming load/store forms (non-temporal
-// loads, sc1 stores); the rotational stencil neighbours use cached loads.
+// Ping-pong steps load f with the non-temporal hint and store with sc1 (the
+// 470 MB working set streams through); in-place steps use the default policy
+// (the single 206 MB f buffer at 1024^2 FP32 largely stays in the 256 MB
+// memory-side cache).  Rotational stencil neighbours use cached loads.
 //
 // Kernel templates, included by the step_*.hip translation units that
 // instantiate and launch them.
@@ -70,6 +75,19 @@ __device__ __forceinline__ float wave_shift(float fill, float v) {
                                                                  0xF, 0xF, false));
 }
 constexpr int kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+
+template <typename P, int CPOL>
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, P v) {
+    if constexpr (sizeof(P) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)vo, (int)so, CPOL);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, (int)vo,
+            (int)so, CPOL);
+}
+// A lane offset past every population row (N * sizeof(P) < 2^32): buffer
+// stores to it are dropped by the range check.
+constexpr uint32_t kDropOffset = 0xFFFFFFFFu;
 
 // Fixed-order workgroup reduction of K doubles; thread 0 writes dst[0..K-1].
 template <int NT, int K>
@@ -140,7 +158,7 @@ __device__ __forceinline__ void rot_relax_store(const P (&gv)[7], const P (&adv)
 template <typename P, int D> constexpr int kWavesMin = sizeof(P) == 4 ? (D == 2 ? 3 : 4) : 2;
 template <typename P, int D> constexpr int kWavesMax = (sizeof(P) == 4 && D == 2) ? 3 : 8;
 
-template <typename P, int D, int TX, int TY>
+template <typename P, int D, int TX, int TY, int S>
 __global__ void __launch_bounds__(TX *TY)
 __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12(StepArgs a) {
     static_assert(!(sizeof(P) == 4 && D == 2) || TX * TY <= 512, "3 waves per SIMD needs <= 512 threads");
@@ -157,9 +175,11 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     const int lx = threadIdx.x % TX, ly = D >= 2 ? threadIdx.x / TX : 0;
     const int x = x0 + lx, y = y0 + ly;
     const bool valid = x < a.n0 && (D < 2 || y < a.n1);
-    // Lanes past a ragged edge work on the clamped node: they load, compute
-    // and store exactly what the lane of that node does (same bits to the
-    // same addresses), so stores need no guard.
+    // Lanes past a ragged edge work on the clamped node: they load and
+    // compute exactly what the lane of that node does.  Ping-pong stores of
+    // theirs write the same bits to the same addresses and need no guard;
+    // in-place translational stores of theirs are dropped (another wave may
+    // not have read those locations yet).
     const int xc = x < a.n0 ? x : a.n0 - 1;
     const int yc = D >= 2 ? (y < a.n1 ? y : a.n1 - 1) : 0;
     const uint32_t N = a.N;
@@ -172,7 +192,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     // from x - c): neighbour offsets are immediates (x) and uniform row
     // offsets (y).  Other waves wrap or clamp per lane.
     const bool inner = xc >= 3 && xc + 3 < a.n0 && (D < 2 || (yc >= 3 && yc + 3 < a.n1));
-    const bool fast = a.streamed == 0 && __all(inner);
+    const bool fast = (S != kSchemePingPong || a.layout == kLayoutPost) && __all(inner);
 
     // Interior lanes: vb = offset of (x-3, y-3) >= 0; row offsets in SGPRs.
     const uint32_t vb = nodeb - 3u * SZ - (D >= 2 ? 3u * (uint32_t)RS : 0u);
@@ -183,28 +203,64 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     // g come from adjacent lanes (DPP) plus four uniform halo values per j.
     constexpr bool XDPP = F32 && TX % 64 == 0;
 
-    // 1. Gather the streamed populations f_i(x) = f*_i(S(x - c_i)) (pull).
+    // 1. The streamed populations f_i(x, t): local (initial or even in-place
+    //    step) or gathered from x - c_i, slot i (ping-pong) or slot opp(i)
+    //    (odd in-place step).
+    constexpr bool PP = S == kSchemePingPong;
+    constexpr int CPL = PP ? kCpolLoadStream : 0;
+    auto slot_in = [](int i) { return S == kSchemeInPlaceOdd ? Q - 1 - i : i; };
     P fv[Q];
-    if (fast) {
+    uint32_t sox[7], soy[7];  // scatter offsets of x + c (odd in-place step, edge waves)
+    if constexpr (S == kSchemeInPlaceEven) {
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.f_in, i, N, SZ);
-            fv[i] = ld_buf<P, kCpolLoadStream>(r, vb + (3 - cx_of(i)) * SZ,
-                                               D >= 2 ? rowo[3 - cy_of(i)] : 0u);
+            fv[i] = ld_buf<P, 0>(pop_rsrc(a.f_in, i, N, SZ), nodeb, 0u);
         });
     } else {
-        const int shift = 1 - a.streamed;
-        uint32_t ox[7], oy[7];
+        if (fast) {
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.f_in, slot_in(i), N, SZ);
+                fv[i] = ld_buf<P, CPL>(r, vb + (3 - cx_of(i)) * SZ, D >= 2 ? rowo[3 - cy_of(i)] : 0u);
+            });
+        } else {
+            const int shift = (PP && a.layout == kLayoutStreamed) ? 0 : 1;
+            uint32_t ox[7], oy[7];
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            ox[k] = (uint32_t)nb_coord(xc, -(k - 3) * shift, a.n0, a.open0) * SZ;
-            oy[k] = D >= 2 ? (uint32_t)nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * (uint32_t)RS : 0u;
+            for (int k = 0; k < 7; ++k) {
+                ox[k] = (uint32_t)nb_coord(xc, -(k - 3) * shift, a.n0, a.open0) * SZ;
+                oy[k] = D >= 2 ? (uint32_t)nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * (uint32_t)RS : 0u;
+                if constexpr (S == kSchemeInPlaceOdd) {
+                    sox[k] = (uint32_t)nb_coord(xc, k - 3, a.n0, 0) * SZ;
+                    soy[k] = D >= 2 ? (uint32_t)nb_coord(yc, k - 3, a.n1, 0) * (uint32_t)RS : 0u;
+                }
+            }
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const uint32_t off = ox[cx_of(i) + 3] + (D >= 2 ? oy[cy_of(i) + 3] : 0u);
+                if constexpr (PP) fv[i] = ld_nt<P>(fin + i * PS, off);
+                else fv[i] = ld<P>(fin + slot_in(i) * PS, off);
+            });
         }
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            fv[i] = ld_nt<P>(fin + i * PS, ox[cx_of(i) + 3] + (D >= 2 ? oy[cy_of(i) + 3] : 0u));
-        });
     }
+    // Translational store of direction i: ping-pong slot i at x (f_out);
+    // even in-place slot opp(i) at x; odd in-place slot i at x + c_i.
+    const uint32_t nodeb_st = valid ? nodeb : kDropOffset;
+    auto store_f = [&](auto I, P v) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (PP) {
+            st<P>(a.f_out, i, N, nodeb, v);
+        } else if constexpr (S == kSchemeInPlaceEven) {
+            st_buf<P, 0>(pop_rsrc(a.f_out, Q - 1 - i, N, SZ), nodeb_st, 0u, v);
+        } else {
+            const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.f_out, i, N, SZ);
+            if (fast)
+                st_buf<P, 0>(r, vb + (3 + cx_of(i)) * SZ, D >= 2 ? rowo[3 + cy_of(i)] : 0u, v);
+            else
+                st_buf<P, 0>(r, valid ? sox[cx_of(i) + 3] + (D >= 2 ? soy[cy_of(i) + 3] : 0u) : kDropOffset,
+                             0u, v);
+        }
+    };
     P gv[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) gv[j] = ld<P>(gin + j * PS, nodeb);
@@ -250,16 +306,17 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     const FeqCoef<P> fc = feq_coef<P, D>((P)rho, up, (P)T);
     P dsp[NS];                               // increments of the special populations
     P cs[7] = {0, 0, 0, 0, 0, 0, 0}, rs[7] = {0, 0, 0, 0, 0, 0, 0};  // FP32 sums
+    // Increment d = omega (f^eq - f), each use written as one multiply-add.
     auto relax = [&](auto I, P fe) {
         constexpr int i = decltype(I)::value;
         constexpr int sr = special_rank<D>(i);
-        const P d = om * (fe - fv[i]);
+        const P df = fe - fv[i];
         if constexpr (F32) {
-            cs[cx_of(i) + 3] += d;
-            if constexpr (D >= 2) rs[cy_of(i) + 3] += d;
+            cs[cx_of(i) + 3] += om * df;
+            if constexpr (D >= 2) rs[cy_of(i) + 3] += om * df;
         }
-        if constexpr (F32 && sr >= 0) dsp[sr] = d;
-        else st<P>(a.f_out, i, N, nodeb, fv[i] + d);
+        if constexpr (F32 && sr >= 0) dsp[sr] = om * df;
+        else store_f(Int<i>{}, fv[i] + om * df);
     };
     static_for<0, H>([&](auto I) {
         constexpr int i = decltype(I)::value, k = Q - 1 - i;
@@ -290,7 +347,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int sr = special_rank<D>(i);
-            if constexpr (sr >= 0) st<P>(a.f_out, i, N, nodeb, fv[i] + (dsp[sr] + (P)ep.e[sr]));
+            if constexpr (sr >= 0) store_f(Int<i>{}, fv[i] + (dsp[sr] + (P)ep.e[sr]));
         });
     }
 
@@ -551,7 +608,7 @@ __global__ void __launch_bounds__(256) k_step_3(StepArgs a) {
     const bool valid = x < a.n0 && y < a.n1 && z < a.n2;
     const int xc = x < a.n0 ? x : a.n0 - 1, yc = y < a.n1 ? y : a.n1 - 1, zc = z;
     const uint32_t node = (uint32_t)xc + (uint32_t)a.n0 * ((uint32_t)yc + (uint32_t)a.n1 * zc);
-    const int shift = 1 - a.streamed;
+    const int shift = a.layout == kLayoutStreamed ? 0 : 1;
     int sx[7], sy[7], sz[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
@@ -565,6 +622,28 @@ __global__ void __launch_bounds__(256) k_step_3(StepArgs a) {
         case 2: step3_wave<P, 2>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
         default: step3_wave<P, 3>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
     }
+}
+
+// Launch k_step_12<P, D, tile, S> for a compiled tile shape; false if none.
+template <typename P, int S>
+bool launch_12(int dim, const int tile[3], const StepArgs &a, hipStream_t s) {
+    const dim3 grid(a.ntiles);
+    bool done = false;
+#define L1(TXv, TYv)                                                                     \
+    if (!done && dim == 1 && tile[0] == TXv) {                                           \
+        hipLaunchKernelGGL((k_step_12<P, 1, TXv, 1, S>), grid, dim3(TXv), 0, s, a);       \
+        done = true;                                                                     \
+    }
+#define L2(TXv, TYv)                                                                     \
+    if (!done && dim == 2 && tile[0] == TXv && tile[1] == TYv) {                         \
+        hipLaunchKernelGGL((k_step_12<P, 2, TXv, TYv, S>), grid, dim3(TXv * TYv), 0, s, a); \
+        done = true;                                                                     \
+    }
+    LBMX_TILES_1D(L1)
+    LBMX_TILES_2D(L2)
+#undef L1
+#undef L2
+    return done;
 }
 
 }  // namespace lbmx

@@ -114,6 +114,13 @@ class Sim:
     def set_graphs(self, on: bool):
         L.check(self.lib.lbm_set_graphs(self.handle, 1 if on else 0))
 
+    def set_inplace(self, on: bool):
+        """Translational streaming in one buffer (True) or ping-pong (False);
+        only before the first step.  Default: in place on fully periodic 1-D/2-D
+        grids."""
+        L.check(self.lib.lbm_set_inplace(self.handle, 1 if on else 0))
+        return self
+
     def set_tile(self, tx, ty=1, tz=1):
         L.check(self.lib.lbm_set_tile(self.handle, int(tx), int(ty), int(tz)))
 

@@ -16,7 +16,7 @@ def announce(msg):
 
 
 def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile=None,
-            graphs=True, chunks=None):
+            graphs=True, chunks=None, inplace=None):
     import torch
     from paper_1606_06107_amd import Sim
     sim = Sim(shape, bc=bc, n_rot=n_rot, tau=tau, dtype=dtype).init(*fields)
@@ -27,6 +27,8 @@ def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile
         sim.init_populations(f * pf, g * pg)
     if tile is not None:
         sim.set_tile(*tile)
+    if inplace is not None:
+        sim.set_inplace(inplace)
     sim.set_graphs(graphs)
     for k in (chunks or [steps]):
         sim.step(k)
