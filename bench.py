@@ -25,15 +25,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
-# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, scaled by the same counters on a plain device copy of known
-# size (profiles/k_step_12_d2q49_1024x1024_fp32.md), valid only for the
-# kernel sources they were taken on (sha256 of the files below).
-TRAFFIC = {"bytes": 479_095_366, "nodes": 1024 * 1024, "tile": (256, 1),
-           "sha256": "278d32782a6e3cbcaa99c737b0dc69d229f94567b1519a2dc96e183516a9a117"}
-TRAFFIC_SOURCES = ("paper_1606_06107_amd/csrc/step_impl.hpp",
-                   "paper_1606_06107_amd/csrc/lbm_device.hpp",
-                   "paper_1606_06107_amd/csrc/step_12_f32.hip")
+# L2-to-memory bytes per step launch of the headline kernels (the even and
+# odd in-place steps, averaged) from rocprofv3 FETCH_SIZE and WRITE_SIZE,
+# scaled by the same counters on a plain device copy of known size
+# (profiles/k_step_12_d2q49_1024x1024_fp32.md), per tile shape; valid only for
+# the sources they were taken on (sha256 of the files below).
+TRAFFIC = {"nodes": 1024 * 1024, "inplace": True,
+           "bytes": {(256, 1): 489_613_821, (128, 2): 489_270_912},
+           "sha256": "cc91227ae55207ad087a2e35f6aa27214f99616d0c6e5390effb0bdb9f8ceed9"}
+TRAFFIC_SOURCES = ('paper_1606_06107_amd/csrc/step_impl.hpp', 'paper_1606_06107_amd/csrc/lbm_device.hpp', 'paper_1606_06107_amd/csrc/launch.hpp', 'paper_1606_06107_amd/csrc/step_12_f32_inplace.hip', 'paper_1606_06107_amd/_build.py')
 
 
 def kernel_sha():
@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--ping-pong", action="store_true",
+                    help="two translational buffers instead of in-place streaming")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first run a plain device copy of this many MB (5 times): the reference "
                          "kernel for scaling HBM traffic counters")
@@ -282,6 +284,8 @@ def main():
     rho, u, T = w.fields()
     N = args.nx * args.ny
     sim = Sim((args.nx, args.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(rho, u, T)
+    sim_inplace = not args.ping_pong
+    sim.set_inplace(sim_inplace)
     tuned = None
     if args.tile:
         sim.set_tile(*[int(v) for v in args.tile.split("x")])
@@ -318,8 +322,8 @@ def main():
 
     used_tile = tuple(tuned) if tuned else (
         tuple(int(v) for v in args.tile.split("x")) if args.tile else (256, 1))
-    traffic_ok = (kernel_sha() == TRAFFIC["sha256"] and N == TRAFFIC["nodes"]
-                  and used_tile == TRAFFIC["tile"])
+    traffic = TRAFFIC["bytes"].get(tuple(used_tile)) if (
+        kernel_sha() == TRAFFIC["sha256"] and N == TRAFFIC["nodes"] and sim_inplace) else None
     mlups = N / (ms_per_step * 1e-3) / 1e6
     bytes_per_node = 2 * (49 + 7) * 4  # read + write every population once
     achieved_gbs = N * bytes_per_node / (ms_per_step * 1e-3) / 1e9
@@ -340,11 +344,12 @@ def main():
                                f"nodes, FP32 populations / FP64 moments, gamma=1.4 (n=3), "
                                f"tau=1, 8-mode random fields at Mach 0.3, seed 0, "
                                f"FP64 totals every {args.monitor_every} steps",
+                   "streaming": "in-place" if sim_inplace else "ping-pong",
                    "nodes": N, "bytes_per_node_step": bytes_per_node,
                    "tile": list(tuned) if tuned else args.tile or "default"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC["bytes"] if traffic_ok else None},
+                     "traffic": traffic},
         "checks": {"finite": finite, "mass_drift": mass_drift, "momentum_drift": mom_drift,
                    "energy_drift_n3": energy_drift, "wall_s": round(wall, 3)},
     }

@@ -60,7 +60,7 @@ def tune_sim(sim, steps=20, reps=3, force=False):
     """Pick the fastest tile of the per-step kernel for this Sim (advances it
     by (len(tiles) * (reps + 1)) * steps steps).  Returns (tile, table)."""
     _load()
-    key = f"step|D{sim.D}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|{_arch()}"
+    key = f"step|D{sim.D}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|ip{sim._inplace}|{_arch()}"
     if key in _mem and not force:
         t = tuple(_mem[key]["best"])
         sim.set_tile(*t)

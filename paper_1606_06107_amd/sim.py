@@ -32,7 +32,8 @@ def lattice_info(dim: int):
 
 
 class Sim:
-    """A grid of nodes on one GPU.
+    """A grid of nodes on one GPU.  Tile, graph and streaming-scheme settings
+    persist across init / init_populations (each creates a new handle).
 
     shape: nodes per axis (x first), bc: 'periodic' | 'open' per axis,
     n_rot: rotational degrees of freedom (gamma = (D+n+2)/(D+n)), tau: BGK
@@ -75,6 +76,18 @@ class Sim:
         self.desc = d
         self.handle = None
         self.n_rot, self.tau = float(n_rot), float(tau)
+        # settings re-applied to every new handle (init / init_populations)
+        self._tile = None
+        self._graphs = None
+        self._inplace = None
+
+    def _apply_settings(self):
+        if self._tile is not None:
+            L.check(self.lib.lbm_set_tile(self.handle, *[int(v) for v in self._tile]))
+        if self._graphs is not None:
+            L.check(self.lib.lbm_set_graphs(self.handle, 1 if self._graphs else 0))
+        if self._inplace is not None:
+            L.check(self.lib.lbm_set_inplace(self.handle, 1 if self._inplace else 0))
 
     def _stream_ptr(self):
         return ctypes.c_void_p(self.stream.cuda_stream)
@@ -93,6 +106,7 @@ class Sim:
             L.check(self.lib.lbm_init(ctypes.byref(self.desc), _ptr(rho_t), _ptr(u_t), _ptr(T_t),
                                       self._stream_ptr(), ctypes.byref(h)))
         self.handle = h
+        self._apply_settings()
         return self
 
     def init_populations(self, f0, g0):
@@ -105,6 +119,7 @@ class Sim:
         L.check(self.lib.lbm_init_populations(ctypes.byref(self.desc), _ptr(f0), _ptr(g0),
                                               self._stream_ptr(), ctypes.byref(h)))
         self.handle = h
+        self._apply_settings()
         return self
 
     def step(self, nsteps=1):
@@ -113,16 +128,19 @@ class Sim:
 
     def set_graphs(self, on: bool):
         L.check(self.lib.lbm_set_graphs(self.handle, 1 if on else 0))
+        self._graphs = bool(on)
 
     def set_inplace(self, on: bool):
         """Translational streaming in one buffer (True) or ping-pong (False);
         only before the first step.  Default: in place on fully periodic 1-D/2-D
         grids."""
         L.check(self.lib.lbm_set_inplace(self.handle, 1 if on else 0))
+        self._inplace = bool(on)
         return self
 
     def set_tile(self, tx, ty=1, tz=1):
         L.check(self.lib.lbm_set_tile(self.handle, int(tx), int(ty), int(tz)))
+        self._tile = (int(tx), int(ty), int(tz))
 
     def set_monitor(self, every, capacity):
         """Record totals every `every` steps into a device tensor [capacity, 2+D]."""
