@@ -93,8 +93,29 @@ def extra_tube_1d():
     b.record(sim.stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b)
-    return {"workload": "1-D tube 1000 nodes, D1Q7+D1Q7 FP64, 1000 steps", "ms_total": round(ms, 3),
-            "us_per_step": round(1000 * ms / w.steps, 2), "MLUPS": round(w.N * w.steps / ms / 1e3, 1)}
+    r1, u1, T1, _ = sim.moments()
+    # the same tube as a batch of one: the whole time loop on chip in one launch
+    import numpy as np
+    from paper_1606_06107_amd import Batch
+    rho0, u0, T0 = w.fields()
+    bt = Batch([w.N], [w.n_rot], [w.tau], [w.steps], dtype=torch.float64)
+    bt.init(rho0, np.asarray(u0).reshape(-1), T0).step()  # capture + warm
+    bt.init(rho0, np.asarray(u0).reshape(-1), T0)
+    a, b = _events(bt.stream)
+    torch.cuda.synchronize()
+    a.record(bt.stream)
+    bt.step()
+    b.record(bt.stream)
+    torch.cuda.synchronize()
+    ms_b = a.elapsed_time(b)
+    r2, u2, T2 = bt.moments()
+    diff = max(float((r1 - r2).abs().max()), float((u1.reshape(-1) - u2).abs().max()), float((T1 - T2).abs().max()))
+    return {"workload": "1-D tube 1000 nodes, D1Q7+D1Q7 FP64, 1000 steps",
+            "per_step_kernels": {"ms_total": round(ms, 3), "us_per_step": round(1000 * ms / w.steps, 2),
+                                 "MLUPS": round(w.N * w.steps / ms / 1e3, 1)},
+            "on_chip_batch_of_one": {"ms_total": round(ms_b, 3), "us_per_step": round(1000 * ms_b / w.steps, 3),
+                                     "MLUPS": round(w.N * w.steps / ms_b / 1e3, 1),
+                                     "max_abs_diff_vs_per_step": diff}}
 
 
 def extra_3d(steps=10):
