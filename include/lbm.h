@@ -185,7 +185,9 @@ typedef struct {
                                f[1] is scratch */
     void *g[2];             /* device [7][total] of dtype: same roles */
     int32_t *status;        /* device [I] out: 0 ok, 1 non-finite, 2 rho<=0 or T<=0,
-                               3 empty tube; a failing tube stops at the step
+                               3 empty tube, 4 not completed (a grid barrier of
+                               the long-tube phase gave up waiting; not
+                               expected); a failing tube stops at the step
                                that failed and its state is then unspecified */
     int64_t *steps_done;    /* device [I] out (may be NULL): steps completed */
     void *workspace;        /* device, lbm_batch_workspace_bytes() bytes */
@@ -202,11 +204,13 @@ size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc);
 lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const double *u,
                           const double *T, void *hip_stream);
 
-/* Advance every tube i by nsteps[i] steps in ONE persistent launch: each
- * workgroup takes tubes longest-work-first from a device queue and runs the
- * whole time loop of a tube on chip (tubes longer than one chunk advance in
- * passes of `superstep` steps with overlapping halos).  The result is left in
- * f[0], g[0]; status[i] is written at the end. */
+/* Advance every tube i by nsteps[i] steps in ONE persistent launch (one
+ * workgroup per compute unit).  Tubes longer than one on-chip chunk advance
+ * first, in passes of at most `superstep` steps: each pass cuts every such
+ * tube into chunks with overlapping halos, all workgroups share the chunks,
+ * and a grid-wide barrier separates passes.  Then the tubes that fit on chip
+ * run their whole time loop there, taken longest-work-first from a device
+ * queue.  The result is left in f[0], g[0]; status[i] is written at the end. */
 lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream);
 
 /* Packed FP64 fields rho[total], u[total], T[total] of the state in f[0], g[0];

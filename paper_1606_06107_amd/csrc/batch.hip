@@ -3,18 +3,24 @@
 // steps, both ends open (zero-gradient clamp), advanced by ONE persistent
 // launch.
 //
-// Work distribution: a one-workgroup bitonic sort orders the tubes by work
-// (length x steps, longest first); persistent workgroups pop tubes from a
-// device counter in that order (longest-processing-time-first list
-// scheduling) and exit when the queue is empty.
-//
 // On-chip time loop: a tube of length L <= C (C = chunk capacity in nodes)
-// is loaded into LDS once, advanced through all its steps there (two
-// workgroup barriers per step) and written back.  A longer tube advances in
-// passes of S steps: each pass walks the tube in chunks of C - 6S interior
-// nodes plus 3S halo nodes per side (the update reaches 3 nodes per step),
-// reads the pass's input buffer and writes the interior to the other buffer.
-// The number of passes is even, so the result ends in f[0], g[0].
+// is loaded into LDS once, advanced through all its steps there (one
+// workgroup barrier per step) and written back.  A longer tube advances in
+// passes of at most S steps: each pass covers the tube in chunks of C - 6S
+// interior nodes plus 3S halo nodes per side (the update reaches 3 nodes per
+// step), reads the pass's input buffer and writes the interior to the other
+// buffer.  Every tube gets an even number of passes, so results end in f[0],
+// g[0].
+//
+// Work distribution, in two phases of the same launch:
+//  1. long tubes, pass by pass: pass p of every long tube still running is
+//     cut into its chunks and all those chunks are shared by all workgroups;
+//     a grid-wide barrier (a device counter, bounded wait) separates passes.
+//     A single long tube therefore runs on as many compute units as it has
+//     chunks instead of on one: its length no longer sets the launch's time.
+//  2. tubes that fit on chip, longest work first (a one-workgroup bitonic
+//     sort orders them), popped from a device counter by the persistent
+//     workgroups (list scheduling).
 //
 // Per node and step the arithmetic is that of the per-step kernels (Sec. V
 // B): FP64 moments and temperature, fourth-order Hermite equilibria, BGK
@@ -39,42 +45,48 @@ struct BatchArgs {
     void *f[2], *g[2];  // packed [7][total]
     int32_t *status;
     int64_t *steps_done;  // may be NULL
-    int32_t *order;     // workspace: processing order
-    int32_t *counter;   // workspace: queue head
+    int32_t *order;     // workspace: on-chip tubes in processing order (nwhole of them)
+    int32_t *counter;   // workspace: [0] queue head, [1] barrier release, [2] abort,
+                        //            [3] nwhole, [4] nlong, [5] chunk tickets,
+                        //            [64 + w] arrival flag of workgroup w
+    int32_t *ltube;     // workspace: long tubes, most passes first (nlong)
+    int32_t *lpas;      // workspace: their pass counts (non-increasing)
+    int32_t *lpfx;      // workspace: prefix sums of their chunk counts (nlong + 1)
+    int64_t *fail_at;   // workspace: first failing step of a long tube (INT64_MAX: none)
     int num;
     uint32_t total;
     int chunk;      // nodes per LDS buffer
     int superstep;  // steps per pass of a chunked tube
 };
 
+constexpr int kCtrQueue = 0, kCtrBarrier = 1, kCtrAbort = 2, kCtrWhole = 3, kCtrLong = 4, kCtrTicket = 5;
+// Arrival flags of the grid barrier, one per workgroup, after the counters.
+constexpr int kFlagBase = 64, kMaxGrid = 1024, kCtrWords = kFlagBase + kMaxGrid;
+constexpr int64_t kNoFail = 0x7fffffffffffffffLL;
+// Status of long tubes when a grid barrier gave up waiting (never expected:
+// every workgroup of the launch is resident).
+constexpr int32_t kStatusAborted = 4;
+
+// Passes of a chunked tube: at most S steps each, at least 2, even.
+__host__ __device__ inline int64_t tube_passes(int64_t steps, int S) {
+    int64_t p = (steps + S - 1) / S;
+    if (p < 2) p = 2;
+    if (p & 1) ++p;
+    return p;
+}
+
 // ---------------------------------------------------------------------------
-// Longest-work-first order: bitonic sort (descending) of 64-bit keys
-// (work << 24 | (2^24 - 1 - index)) in LDS by one workgroup; also resets the
-// queue head.  num <= kSortMax; larger batches keep index order.
+// Schedule (one workgroup): resets the queue head, the barrier and abort
+// flags; on-chip tubes sorted by work (length x steps, descending) into
+// order[0..nwhole); long tubes (L > C) sorted by step count (descending) into
+// ltube[0..nlong) with their pass counts and the prefix sums of their chunk
+// counts.  Bitonic sorts of 64-bit keys (value << 24 | 2^24 - 1 - index) in
+// LDS.  Batches of more than kSortMax tubes keep index order and run every
+// tube in phase 1 (a long tube then walks its chunks on one workgroup).
 // ---------------------------------------------------------------------------
 constexpr int kSortMax = 16384;
 
-__global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
-    __shared__ unsigned long long key[kSortMax];
-    const int n = a.num;
-    if (threadIdx.x == 0) *a.counter = 0;
-    if (n > kSortMax) {
-        for (int i = threadIdx.x; i < n; i += 1024) a.order[i] = i;
-        return;
-    }
-    int P2 = 1;
-    while (P2 < n) P2 <<= 1;
-    for (int i = threadIdx.x; i < P2; i += 1024) {
-        unsigned long long k = 0;
-        if (i < n) {
-            const long long L = a.offsets[i + 1] - a.offsets[i];
-            long long w = L * (a.nsteps[i] > 0 ? a.nsteps[i] : 0);
-            if (w > (1LL << 39) - 1) w = (1LL << 39) - 1;
-            k = ((unsigned long long)w << 24) | (unsigned long long)((1 << 24) - 1 - i);
-        }
-        key[i] = k;
-    }
-    __syncthreads();
+__device__ void bitonic_desc(unsigned long long *key, int P2) {
     for (int size = 2; size <= P2; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = threadIdx.x; i < P2; i += 1024) {
@@ -91,8 +103,105 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < n; i += 1024)
-        a.order[i] = (1 << 24) - 1 - (int)(key[i] & ((1ULL << 24) - 1));
+}
+
+__global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
+    __shared__ unsigned long long key[kSortMax];
+    __shared__ int s_cnt[2];
+    __shared__ int part[1024];
+    const int n = a.num;
+    const int inner = a.chunk - 6 * a.superstep;
+    if (threadIdx.x == 0) {
+        a.counter[kCtrQueue] = 0;
+        a.counter[kCtrBarrier] = 0;
+        a.counter[kCtrAbort] = 0;
+        a.counter[kCtrTicket] = 0;
+        s_cnt[0] = 0;
+        s_cnt[1] = 0;
+    }
+    for (int i = threadIdx.x; i < n; i += 1024) a.fail_at[i] = kNoFail;
+    for (int w = threadIdx.x; w < kMaxGrid; w += 1024) a.counter[kFlagBase + w] = 0;
+    if (n > kSortMax) {
+        for (int i = threadIdx.x; i < n; i += 1024) a.order[i] = i;
+        if (threadIdx.x == 0) {
+            a.counter[kCtrWhole] = n;
+            a.counter[kCtrLong] = 0;
+            a.lpfx[0] = 0;
+        }
+        return;
+    }
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    __syncthreads();
+    // 1. on-chip tubes by work
+    for (int i = threadIdx.x; i < P2; i += 1024) {
+        unsigned long long k = 0;
+        if (i < n) {
+            const long long L = a.offsets[i + 1] - a.offsets[i];
+            if (L <= a.chunk) {
+                long long w = L * (a.nsteps[i] > 0 ? a.nsteps[i] : 0);
+                if (w > (1LL << 39) - 1) w = (1LL << 39) - 1;
+                k = ((unsigned long long)w << 24) | (unsigned long long)((1 << 24) - 1 - i);
+                atomicAdd(&s_cnt[0], 1);
+            }
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    bitonic_desc(key, P2);
+    const int nw = s_cnt[0];
+    for (int i = threadIdx.x; i < nw; i += 1024) a.order[i] = (1 << 24) - 1 - (int)(key[i] & ((1ULL << 24) - 1));
+    __syncthreads();
+    // 2. long tubes by steps
+    for (int i = threadIdx.x; i < P2; i += 1024) {
+        unsigned long long k = 0;
+        if (i < n) {
+            const long long L = a.offsets[i + 1] - a.offsets[i];
+            if (L > a.chunk) {
+                long long st = a.nsteps[i] > 0 ? a.nsteps[i] : 0;
+                if (st > (1LL << 39) - 2) st = (1LL << 39) - 2;
+                k = ((unsigned long long)(st + 1) << 24) | (unsigned long long)((1 << 24) - 1 - i);
+                atomicAdd(&s_cnt[1], 1);
+            }
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    bitonic_desc(key, P2);
+    const int nl = s_cnt[1];
+    // chunk counts -> segment sums per thread -> prefix
+    const int seg = (nl + 1023) / 1024;
+    int sum = 0;
+    for (int j = threadIdx.x * seg; j < nl && j < (threadIdx.x + 1) * seg; ++j) {
+        const int t = (1 << 24) - 1 - (int)(key[j] & ((1ULL << 24) - 1));
+        const int64_t L = a.offsets[t + 1] - a.offsets[t];
+        const int64_t st = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
+        a.ltube[j] = t;
+        a.lpas[j] = (int)tube_passes(st, a.superstep);
+        sum += (int)((L + inner - 1) / inner);
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < 1024; ++w) {
+            const int v = part[w];
+            part[w] = acc;
+            acc += v;
+        }
+        a.lpfx[nl] = acc;
+        a.counter[kCtrWhole] = nw;
+        a.counter[kCtrLong] = nl;
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int j = threadIdx.x * seg; j < nl && j < (threadIdx.x + 1) * seg; ++j) {
+        a.lpfx[j] = acc;
+        const int t = a.ltube[j];
+        const int64_t L = a.offsets[t + 1] - a.offsets[t];
+        acc += (int)((L + inner - 1) / inner);
+        a.status[t] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -196,8 +305,12 @@ __device__ __forceinline__ int health(double rho, double T) {
 // ping-ponging between the two LDS buffers (one barrier per step).  `shift`
 // is the representation in `cur` on entry (0 streamed, 1 post-collision).
 // Nodes [vlo, vhi) are health-checked each step (their values are exact at
-// every step); on failure *bad is set and the loop stops.  Returns the
-// buffer index holding the result; *shift_out its representation.
+// every step); on failure the loop stops.  bad[2] (LDS, zero on entry)
+// receives the failure kind in slot (step & 1): a thread can write slot
+// (s & 1) again only at step s + 2, after every thread has passed the
+// barrier of step s + 1 and so has read the flag of step s -- all threads
+// leave at the same step.  Returns the buffer index holding the result;
+// *shift_out its representation.
 template <typename P, int B>
 __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, double omega,
                        double n_rot, int vlo, int vhi, int *bad, int *shift_out, int *ran) {
@@ -221,15 +334,152 @@ __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, dou
                 h = hh > h ? hh : h;
             }
         }
-        if (h) atomicMax(bad, h);
+        if (h) atomicMax(&bad[s & 1], h);
         shift = 1;
         cur ^= 1;
         *ran = s + 1;
         __syncthreads();
-        if (*bad) break;
+        if (bad[s & 1]) break;
     }
     *shift_out = shift;
     return cur;
+}
+
+// Grid-wide barrier of a persistent launch whose workgroups are all
+// resident (generation gen = 1, 2, ...).  Each workgroup release-stores gen
+// into its own arrival flag; the first wave of workgroup 0 polls all flags
+// (relaxed device-scope loads, wave-wide minimum) and then release-stores gen
+// into one release word, which the others poll (relaxed; one acquire fence
+// after the wait).  No contended read-modify-write.  Bounded wait: returns
+// false (and sets the abort flag, which every waiter also watches) if the
+// others did not arrive within the bound.
+constexpr long kBarrierSpins = 1L << 24;  // a sleep + a device-scope load each: ~10-30 s
+
+__device__ bool grid_barrier(int32_t *ctr, int gen) {
+    __shared__ int s_ok;
+    // The workgroup barrier completes every wave's stores (to L2); one
+    // device-scope release by the arriving thread then publishes them (an
+    // L2 write-back per workgroup, not per wave).
+    __syncthreads();
+    const int nwg = (int)gridDim.x;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) {
+            int ok = 1;
+            long spins = 0;
+            for (;;) {
+                int mn = gen;
+                for (int w = 1 + (int)threadIdx.x; w < nwg; w += 64) {
+                    const int v = __hip_atomic_load(&ctr[kFlagBase + w], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                    mn = v < mn ? v : mn;
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const int o = __shfl_xor(mn, off, 64);
+                    mn = o < mn ? o : mn;
+                }
+                if (mn >= gen) break;  // wave-uniform after the reduction
+                const int ab = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&ctr[kCtrAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                if (ab) {
+                    ok = 0;
+                    break;
+                }
+                if (++spins > kBarrierSpins) {
+                    if (threadIdx.x == 0)
+                        __hip_atomic_store(&ctr[kCtrAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (threadIdx.x == 0) {
+                s_ok = ok;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");  // others' chunks in, ours out
+                if (ok) __hip_atomic_store(&ctr[kCtrBarrier], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&ctr[kFlagBase + blockIdx.x], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        long spins = 0;
+        while (__hip_atomic_load(&ctr[kCtrBarrier], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            if (__hip_atomic_load(&ctr[kCtrAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (++spins > kBarrierSpins) {
+                __hip_atomic_store(&ctr[kCtrAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other chunks of this pass
+        s_ok = ok;
+    }
+    // the acquire above invalidated this CU's caches for every wave
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// LDS <- rows [0, 7) x nodes [0, R) of f and g starting at packed node
+// `first`; four elements per thread and iteration, all loads issued before
+// the LDS stores, so that several global loads are in flight.
+template <typename P, int B>
+__device__ __forceinline__ void load_region(P *F, P *G, int C, const P *fs, const P *gs, uint32_t tot,
+                                            int64_t first, int R) {
+    const int n = 7 * R;
+    for (int e0 = threadIdx.x; e0 < n; e0 += 4 * B) {
+        P fv[4], gv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * B;
+            if (e < n) {
+                const int i = e / R, x = e - i * R;
+                fv[u] = fs[(size_t)i * tot + first + x];
+                gv[u] = gs[(size_t)i * tot + first + x];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * B;
+            if (e < n) {
+                const int i = e / R, x = e - i * R;
+                F[i * C + x] = fv[u];
+                G[i * C + x] = gv[u];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// One chunk of one pass of a long tube: nodes [c0, c1) with a halo of 3 sp
+// nodes per side read from (fs, gs), advanced sp steps in LDS, the interior
+// written to (fd, gd).  Returns the steps completed (sp unless a node of the
+// interior failed the health check, *bad then holds its kind).
+template <typename P, int B>
+__device__ int run_chunk(P *F, P *G, int C, const P *fs, const P *gs, P *fd, P *gd, uint32_t tot, int64_t base,
+                         int L, int c0, int c1, int sp, P om, double omega, double n_rot, int *bad) {
+    const int halo = 3 * sp;
+    const int lo = c0 - halo > 0 ? c0 - halo : 0;
+    const int hi = c1 + halo < L ? c1 + halo : L;
+    const int R = hi - lo;
+    load_region<P, B>(F, G, C, fs, gs, tot, base + lo, R);
+    int shift, ran;
+    const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo, bad, &shift, &ran);
+    const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+    const int W = c1 - c0;
+    for (int e = threadIdx.x; e < 7 * W; e += B) {
+        const int i = e / W, x = (c0 - lo) + (e - i * W);
+        int sx = x - (i - 3) * shift;
+        sx = sx < 0 ? 0 : (sx >= R ? R - 1 : sx);
+        fd[(size_t)i * tot + base + lo + x] = Fr[i * C + sx];
+        gd[(size_t)i * tot + base + lo + x] = Gr[i * C + x];
+    }
+    __syncthreads();
+    return ran;
 }
 
 template <typename P, int B>
@@ -238,17 +488,101 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
     const int C = a.chunk;
     P *F = reinterpret_cast<P *>(smem_raw);  // [2][7][C]
     P *G = F + 14 * C;                        // [2][7][C]
-    __shared__ int s_item, s_bad;
+    __shared__ int s_item, s_bad[2];
     const uint32_t tot = a.total;
+    const int nwhole = a.counter[kCtrWhole];
 
+    // Phase 1: long tubes, pass by pass; the chunks of a pass are shared by
+    // all workgroups, a grid barrier separates passes.  It runs first, so a
+    // barrier only ever waits for one pass of chunk work.
+    const int nlong = a.counter[kCtrLong];
+    const int inner = C - 6 * a.superstep;
+    const int maxp = nlong > 0 ? a.lpas[0] : 0;
+    bool ok = true;
+    // Chunks are handed out by tickets from one monotonic counter: pass p
+    // owns tickets [tbase, tbase + items); a workgroup that draws a ticket of
+    // a later pass keeps it until that pass.
+    int tbase = 0, held = -1;
+    for (int p = 0; p < maxp && ok; ++p) {
+        // long tubes still running at pass p: a prefix of the list
+        int lo = 0, hi = nlong;  // first j with lpas[j] <= p
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (a.lpas[mid] > p) lo = mid + 1;
+            else hi = mid;
+        }
+        const int items = a.lpfx[lo];
+        for (;;) {
+            if (held < 0) {
+                if (threadIdx.x == 0) s_item = atomicAdd(&a.counter[kCtrTicket], 1);
+                __syncthreads();
+                held = s_item;
+                __syncthreads();
+            }
+            if (held >= tbase + items) break;  // a later pass's ticket (uniform)
+            const int k = held - tbase;
+            held = -1;
+            int jl = 0, jh = lo - 1;  // last j with lpfx[j] <= k
+            while (jl < jh) {
+                const int mid = (jl + jh + 1) >> 1;
+                if (a.lpfx[mid] <= k) jl = mid;
+                else jh = mid - 1;
+            }
+            const int t = a.ltube[jl];
+            // failed in an earlier pass?  Other workgroups may set fail_at
+            // during this pass: one read per workgroup keeps the branch uniform.
+            if (threadIdx.x == 0) s_item = a.fail_at[t] != kNoFail;
+            __syncthreads();
+            const int skip = s_item;
+            __syncthreads();
+            if (skip) continue;
+            const int64_t base = a.offsets[t];
+            const int L = (int)(a.offsets[t + 1] - base);
+            const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
+            const int64_t passes = a.lpas[jl];
+            const int64_t done = steps * p / passes;
+            const int sp = (int)(steps * (p + 1) / passes - done);
+            const int c0 = (k - a.lpfx[jl]) * inner;
+            const int c1 = c0 + inner < L ? c0 + inner : L;
+            const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
+            if (threadIdx.x == 0) s_bad[0] = s_bad[1] = 0;
+            __syncthreads();
+            const int ran = run_chunk<P, B>(F, G, C, reinterpret_cast<const P *>(a.f[p & 1]),
+                                            reinterpret_cast<const P *>(a.g[p & 1]),
+                                            reinterpret_cast<P *>(a.f[(p + 1) & 1]),
+                                            reinterpret_cast<P *>(a.g[(p + 1) & 1]), tot, base, L, c0, c1, sp,
+                                            (P)omega, omega, n_rot, s_bad);
+            const int fail = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
+            if (threadIdx.x == 0 && fail) {
+                atomicMax(&a.status[t], fail);
+                __hip_atomic_fetch_min(&a.fail_at[t], (int64_t)(done + ran), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+        tbase += items;
+        ok = grid_barrier(a.counter, p + 1);
+    }
+    // results: steps completed, and the status of an aborted schedule
+    for (int j = blockIdx.x * B + threadIdx.x; j < nlong; j += gridDim.x * B) {
+        const int t = a.ltube[j];
+        if (!ok) a.status[t] = kStatusAborted;
+        if (a.steps_done) {
+            const int64_t f = a.fail_at[t];
+            a.steps_done[t] = f != kNoFail ? f : (a.nsteps[t] > 0 ? a.nsteps[t] : 0);
+        }
+    }
+
+    // Phase 2: tubes from the queue (on-chip ones; every tube when the
+    // schedule kept index order).
     for (;;) {
         if (threadIdx.x == 0) {
-            s_item = atomicAdd(a.counter, 1);
-            s_bad = 0;
+            s_item = atomicAdd(&a.counter[kCtrQueue], 1);
+            s_bad[0] = s_bad[1] = 0;
         }
         __syncthreads();
         const int item = s_item;
-        if (item >= a.num) break;  // uniform: every workgroup reaches this exit
+        if (item >= nwhole) break;  // uniform: every workgroup reaches this exit
         const int t = a.order[item];
         const int64_t base = a.offsets[t];
         const int L = (int)(a.offsets[t + 1] - base);
@@ -269,14 +603,9 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
 
         if (L <= C) {
             // whole tube on chip
-            for (int e = threadIdx.x; e < 7 * L; e += B) {
-                const int i = e / L, x = e - i * L;
-                F[i * C + x] = f0[(size_t)i * tot + base + x];
-                G[i * C + x] = g0[(size_t)i * tot + base + x];
-            }
-            __syncthreads();
+            load_region<P, B>(F, G, C, f0, g0, tot, base, L);
             int shift, ran;
-            const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, &s_bad, &shift,
+            const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, s_bad, &shift,
                                           &ran);
             done_total = ran;
             const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
@@ -297,7 +626,7 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
             if (passes < 2) passes = 2;
             if (passes & 1) ++passes;
             int64_t done = 0;
-            for (int p = 0; p < passes && !s_bad; ++p) {
+            for (int p = 0; p < passes && !(s_bad[0] | s_bad[1]); ++p) {
                 const int sp = (int)((steps - done) / (passes - p));
                 const P *fs = reinterpret_cast<const P *>(a.f[p & 1]);
                 const P *gs = reinterpret_cast<const P *>(a.g[p & 1]);
@@ -311,15 +640,10 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                     const int lo = c0 - halo > 0 ? c0 - halo : 0;
                     const int hi = c1 + halo < L ? c1 + halo : L;
                     const int R = hi - lo;
-                    for (int e = threadIdx.x; e < 7 * R; e += B) {
-                        const int i = e / R, x = e - i * R;
-                        F[i * C + x] = fs[(size_t)i * tot + base + lo + x];
-                        G[i * C + x] = gs[(size_t)i * tot + base + lo + x];
-                    }
-                    __syncthreads();
+                    load_region<P, B>(F, G, C, fs, gs, tot, base + lo, R);
                     int shift, ran;
                     const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo,
-                                                  &s_bad, &shift, &ran);
+                                                  s_bad, &shift, &ran);
                     pass_ran = ran < pass_ran ? ran : pass_ran;
                     const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
                     const int W = c1 - c0;
@@ -339,11 +663,12 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
             }
         }
         if (threadIdx.x == 0) {
-            a.status[t] = s_bad;
+            a.status[t] = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
             if (a.steps_done) a.steps_done[t] = done_total;
         }
         __syncthreads();
     }
+
 }
 
 }  // namespace lbmx
@@ -449,8 +774,13 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
     }
     a.status = d->status;
     a.steps_done = d->steps_done;
+    const size_t n = (size_t)d->num_instances;
     a.counter = reinterpret_cast<int32_t *>(d->workspace);
-    a.order = a.counter + 64;
+    a.order = a.counter + lbmx::kCtrWords;
+    a.ltube = a.order + n;
+    a.lpas = a.ltube + n;
+    a.lpfx = a.lpas + n;
+    a.fail_at = reinterpret_cast<int64_t *>(a.counter + lbmx::kCtrWords + ((4 * n + 1 + 1) & ~(size_t)1));
     a.num = (int)d->num_instances;
     a.total = (uint32_t)d->total_nodes;
     a.chunk = L.chunk;
@@ -458,7 +788,9 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
     int dev = 0, cus = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int grid = (int)(d->num_instances < cus ? d->num_instances : cus);
+    // one resident workgroup per compute unit (the LDS chunk fills it): the
+    // long-tube passes spread a tube's chunks over all of them
+    const int grid = cus < lbmx::kMaxGrid ? cus : lbmx::kMaxGrid;
     if (!prepare) {
         hipLaunchKernelGGL(lbmx::k_batch_order, dim3(1), dim3(1024), 0, s, a);
         hipError_t e = hipGetLastError();
@@ -474,7 +806,11 @@ extern "C" {
 
 size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc) {
     if (!desc || desc->num_instances < 1) return 0;
-    return ((64 * 4 + (size_t)desc->num_instances * 4 + 255) / 256) * 256;
+    // counters and barrier flags [kCtrWords], order, ltube, lpas [n] each,
+    // lpfx [n+1] (int32, padded to 8 bytes), fail_at [n] (int64)
+    const size_t n = (size_t)desc->num_instances;
+    const size_t i32 = lbmx::kCtrWords + ((4 * n + 1 + 1) & ~(size_t)1);
+    return ((i32 * 4 + n * 8 + 255) / 256) * 256;
 }
 
 lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const double *u,
