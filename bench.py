@@ -119,29 +119,39 @@ def extra_tube_1d():
 
 
 def extra_3d(steps=10):
-    """256^3 decaying turbulence, D3Q343 + D1Q7 FP32, gamma = 1.4."""
+    """256^3 decaying turbulence, D3Q343 + D1Q7 FP32, gamma = 1.4: the
+    default blocked population order, and the plain [Q][N] order beside it."""
     import torch
 
     import workloads
     from paper_1606_06107_amd import Sim
     w = workloads.Turbulence3D()
-    sim = Sim((w.n,) * 3, n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields())
-    sim.step(2)
-    a, b = _events(sim.stream)
-    torch.cuda.synchronize()
-    a.record(sim.stream)
-    sim.step(steps)
-    b.record(sim.stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / steps
     N = w.n ** 3
+
+    def run(blocked):
+        sim = Sim((w.n,) * 3, n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields())
+        sim.set_blocked(blocked)
+        sim.step(2)
+        a, b = _events(sim.stream)
+        torch.cuda.synchronize()
+        a.record(sim.stream)
+        sim.step(steps)
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        T = sim.moments(totals=False)[2]
+        ok = bool(torch.isfinite(T).all().item())
+        del sim, T
+        torch.cuda.empty_cache()
+        return ms, ok
+
+    ms, ok = run(True)
+    ms_plain, ok_plain = run(False)
     gbs = N * 2800 / (ms * 1e-3) / 1e9
-    T = sim.moments(totals=False)[2]
-    ok = bool(torch.isfinite(T).all().item())
-    del sim
-    return {"workload": "3-D 256^3 turbulence, D3Q343+D1Q7 FP32, gamma=1.4", "ms_per_step": round(ms, 3),
-            "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "finite": ok}
+    return {"workload": "3-D 256^3 turbulence, D3Q343+D1Q7 FP32, gamma=1.4", "order": "blocked (64 nodes)",
+            "ms_per_step": round(ms, 3), "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1),
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok and ok_plain,
+            "plain_order_ms_per_step": round(ms_plain, 3)}
 
 
 def extra_batch(seed=0):
@@ -274,6 +284,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,batched_tubes,surrogate",
+                    help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ping-pong", action="store_true",
                     help="two translational buffers instead of in-place streaming")
@@ -377,8 +389,11 @@ def main():
     del sim
     if not args.no_extras:
         extra = {}
+        wanted = set(args.extras.split(","))
         for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d),
                          ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
+            if name not in wanted:
+                continue
             print(f"bench: {name}", file=sys.stderr, flush=True)
             extra[name] = fn()
             torch.cuda.empty_cache()

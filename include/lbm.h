@@ -77,9 +77,12 @@ typedef struct {
     double n_rot;        /* rotational degrees of freedom n >= 0 (real);
                             gamma = (D+n+2)/(D+n) */
     double tau;          /* BGK relaxation time in time steps, tau > 0.5 */
-    void *f[2];          /* two device buffers [Q][N] of dtype (ping-pong); with
-                            in-place streaming (lbm_set_inplace) only f[0] is
-                            used, but both must be given */
+    void *f[2];          /* two device buffers of Q*N values of dtype (ping-pong);
+                            with in-place streaming (lbm_set_inplace) only f[0]
+                            is used, but both must be given.  The order of the
+                            values inside is the library's (lbm_set_blocked):
+                            read and write populations through
+                            lbm_populations / lbm_init_populations */
     void *g[2];          /* two device buffers [7][N] of dtype (ping-pong) */
     void *workspace;     /* device scratch of lbm_workspace_bytes() bytes, 256-B
                             aligned (reduction partials); caller-owned */
@@ -147,10 +150,23 @@ lbm_status lbm_set_graphs(lbm_sim sim, int32_t enable);
  * LBM_EUNSUPPORTED (enable on an open axis or in 3-D). */
 lbm_status lbm_set_inplace(lbm_sim sim, int32_t enable);
 
+/* Order of the translational values inside f[0], f[1], chosen before the
+ * first step.  enable = 0: plain [Q][N] (slot i of node x at i*N + x).
+ * enable = 1 (3-D grids with n0 a multiple of 64): blocks of 64 x-consecutive
+ * nodes, slot i of node x at ((x/64)*Q + i)*64 + x%64, so the 343 populations
+ * of one workgroup tile are one contiguous run (the step writes each block
+ * in one piece and reads 49 source rows instead of 343 separate streams).
+ * Same arithmetic, identical results.  Switching reorders the current state
+ * into the other f buffer on the sim's stream; enabling sets the tile to
+ * 64x1x1, the only one the blocked step runs with.  Default: blocked where
+ * possible.  Errors: LBM_EINVAL (after the first step), LBM_EUNSUPPORTED
+ * (enable on a grid that cannot be blocked), LBM_ELAUNCH. */
+lbm_status lbm_set_blocked(lbm_sim sim, int32_t enable);
+
 /* Launch shape of the step kernel: nodes per workgroup tile along x, y, z
  * (product 64..1024, a multiple of 64; tile_x a multiple of 16).  Used by the
  * autotuner; results do not depend on it.  LBM_EUNSUPPORTED if the shape is
- * not compiled. */
+ * not compiled, or not 64x1x1 under the blocked order. */
 lbm_status lbm_set_tile(lbm_sim sim, int32_t tx, int32_t ty, int32_t tz);
 
 /* Release the handle and its graphs (NULL-safe).  Device buffers are the

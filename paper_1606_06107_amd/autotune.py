@@ -12,6 +12,8 @@ import os
 
 import torch
 
+from ._lib import LBM_EUNSUPPORTED, LbmError
+
 TILES = {1: [(64, 1), (128, 1), (256, 1), (512, 1), (1024, 1)],
          2: [(64, 4), (32, 8), (128, 2), (256, 1), (64, 8), (32, 16), (16, 16), (64, 2)],
          3: [(64, 1), (32, 2), (16, 4)]}
@@ -60,14 +62,20 @@ def tune_sim(sim, steps=20, reps=3, force=False):
     """Pick the fastest tile of the per-step kernel for this Sim (advances it
     by (len(tiles) * (reps + 1)) * steps steps).  Returns (tile, table)."""
     _load()
-    key = f"step|D{sim.D}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|ip{sim._inplace}|{_arch()}"
+    key = (f"step|D{sim.D}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|ip{sim._inplace}"
+           f"|blk{sim._blocked}|{_arch()}")
     if key in _mem and not force:
         t = tuple(_mem[key]["best"])
         sim.set_tile(*t)
         return t, _mem[key]["table"]
     table = {}
     for t in TILES[sim.D]:
-        sim.set_tile(*t)
+        try:
+            sim.set_tile(*t)
+        except LbmError as e:  # not available for this sim (e.g. blocked 3-D order)
+            if e.status != LBM_EUNSUPPORTED:
+                raise
+            continue
         table["x".join(map(str, t))] = _time(lambda: sim.step(steps), reps, sim.stream) / steps
     best = min(table, key=table.get)
     bt = tuple(int(v) for v in best.split("x"))

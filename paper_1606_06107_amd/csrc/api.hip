@@ -124,6 +124,7 @@ struct lbm_sim_s {
     int fcur = 0, gcur = 0;               // buffer indices of the current f and g
     int layout = lbmx::kLayoutStreamed;   // what f[fcur] holds (just initialised)
     int inplace = 0;                      // translational streaming in one buffer
+    int blocked = 0;                      // value order of f (lbmx::pop_index)
     int64_t t = 0;
     int tile[3];
     int graphs = 1;
@@ -178,6 +179,7 @@ hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
     a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
     a.N = (uint32_t)N_of(d);
     a.layout = s->layout;
+    a.blocked = s->blocked;
     a.scheme = !s->inplace ? lbmx::kSchemePingPong
                            : (s->layout == lbmx::kLayoutStreamed ? lbmx::kSchemeInPlaceEven
                                                                  : lbmx::kSchemeInPlaceOdd);
@@ -209,6 +211,29 @@ bool inplace_possible(const lbm_desc &d) {
     return true;
 }
 
+// The blocked order puts one 64-node tile's populations in one block: 3-D
+// grids whose rows are whole blocks.
+bool blocked_possible(const lbm_desc &d) { return d.dim == 3 && d.n[0] % lbmx::kBlk == 0; }
+
+// Field/export arguments for the current state.
+lbmx::FieldArgs field_args(lbm_sim s) {
+    const lbm_desc &d = s->d;
+    lbmx::FieldArgs a = {};
+    a.f = d.f[s->fcur];
+    a.g = d.g[s->gcur];
+    a.n0 = (int)d.n[0];
+    a.n1 = (int)d.n[1];
+    a.n2 = (int)d.n[2];
+    a.open0 = d.bc[0] == LBM_BC_OPEN;
+    a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
+    a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
+    a.N = (uint32_t)N_of(d);
+    a.layout = s->layout;
+    a.blocked = s->blocked;
+    a.n_rot = d.n_rot;
+    return a;
+}
+
 lbm_status make_sim(const lbm_desc *desc, void *stream, lbm_sim *out) {
     lbm_status st = validate(desc);
     if (st) return st;
@@ -221,6 +246,7 @@ lbm_status make_sim(const lbm_desc *desc, void *stream, lbm_sim *out) {
     s->stream = (hipStream_t)stream;
     default_tile(desc->dim, s->tile);
     s->inplace = inplace_possible(*desc) ? 1 : 0;
+    s->blocked = blocked_possible(*desc) ? 1 : 0;
     if (hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess) {
         delete s;
         return fail(LBM_EDEVICE, "hipStreamCreateWithFlags failed");
@@ -247,7 +273,7 @@ lbm_status lbm_init(const lbm_desc *desc, const double *rho, const double *u, co
     lbm_sim s = nullptr;
     lbm_status st = make_sim(desc, hip_stream, &s);
     if (st) return st;
-    lbmx::InitArgs a{rho, u, T, desc->f[0], desc->g[0], (uint32_t)N_of(*desc)};
+    lbmx::InitArgs a{rho, u, T, desc->f[0], desc->g[0], (uint32_t)N_of(*desc), s->blocked};
     hipError_t e = lbmx::launch_init(desc->dtype, desc->dim, a, s->stream);
     if (e != hipSuccess) {
         lbm_destroy(s);
@@ -265,9 +291,14 @@ lbm_status lbm_init_populations(const lbm_desc *desc, const void *f0, const void
     if (st) return st;
     const size_t N = (size_t)N_of(*desc), b = pop_bytes(desc->dtype);
     hipError_t e = hipSuccess;
-    if (f0 != desc->f[0])
+    if (s->blocked) {  // reorder into f[0], or into f[1] when f0 is f[0]
+        s->fcur = f0 == desc->f[0] ? 1 : 0;
+        e = lbmx::launch_to_blocked(desc->dtype, q_of(desc->lattice), (uint32_t)N, f0, desc->f[s->fcur],
+                                    s->stream);
+    } else if (f0 != desc->f[0]) {
         e = hipMemcpyAsync(desc->f[0], f0, (size_t)q_of(desc->lattice) * N * b,
                            hipMemcpyDeviceToDevice, s->stream);
+    }
     if (e == hipSuccess && g0 != desc->g[0])
         e = hipMemcpyAsync(desc->g[0], g0, 7 * N * b, hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) {
@@ -339,18 +370,7 @@ lbm_status lbm_step(lbm_sim s, int64_t nsteps) {
 lbm_status lbm_moments(lbm_sim s, double *rho, double *u, double *T, double *totals) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     const lbm_desc &d = s->d;
-    lbmx::FieldArgs a = {};
-    a.f = d.f[s->fcur];
-    a.g = d.g[s->gcur];
-    a.n0 = (int)d.n[0];
-    a.n1 = (int)d.n[1];
-    a.n2 = (int)d.n[2];
-    a.open0 = d.bc[0] == LBM_BC_OPEN;
-    a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
-    a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
-    a.N = (uint32_t)N_of(d);
-    a.layout = s->layout;
-    a.n_rot = d.n_rot;
+    lbmx::FieldArgs a = field_args(s);
     a.rho = rho;
     a.u = u;
     a.T = T;
@@ -374,17 +394,7 @@ lbm_status lbm_populations(lbm_sim s, void *f_out, void *g_out) {
         if ((f_out && (f_out == d.f[k] || f_out == d.g[k])) ||
             (g_out && (g_out == d.f[k] || g_out == d.g[k])))
             return fail(LBM_EINVAL, "export buffers must differ from the state buffers");
-    lbmx::FieldArgs a = {};
-    a.f = d.f[s->fcur];
-    a.g = d.g[s->gcur];
-    a.n0 = (int)d.n[0];
-    a.n1 = (int)d.n[1];
-    a.n2 = (int)d.n[2];
-    a.open0 = d.bc[0] == LBM_BC_OPEN;
-    a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
-    a.open2 = d.dim >= 3 && d.bc[2] == LBM_BC_OPEN;
-    a.N = (uint32_t)N_of(d);
-    a.layout = s->layout;
+    lbmx::FieldArgs a = field_args(s);
     a.f_out = f_out;
     a.g_out = g_out;
     hipError_t e = lbmx::launch_export(d.dtype, d.dim, a, s->stream);
@@ -426,11 +436,42 @@ lbm_status lbm_set_inplace(lbm_sim s, int32_t enable) {
     return LBM_OK;
 }
 
+lbm_status lbm_set_blocked(lbm_sim s, int32_t enable) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (s->t != 0 || s->layout != lbmx::kLayoutStreamed)
+        return fail(LBM_EINVAL, "the population order can only be chosen before the first step");
+    enable = enable ? 1 : 0;
+    if (enable && !blocked_possible(s->d))
+        return fail(LBM_EUNSUPPORTED, "the blocked order needs a 3-D grid with n0 a multiple of %d", lbmx::kBlk);
+    if (enable == s->blocked) return LBM_OK;
+    const lbm_desc &d = s->d;
+    const int src = s->fcur, dst = s->fcur ^ 1;
+    hipError_t e;
+    if (enable) {
+        e = lbmx::launch_to_blocked(d.dtype, q_of(d.lattice), (uint32_t)N_of(d), d.f[src], d.f[dst], s->stream);
+    } else {
+        lbmx::FieldArgs a = field_args(s);
+        a.f_out = d.f[dst];
+        e = lbmx::launch_export(d.dtype, d.dim, a, s->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "reorder launch");
+    s->fcur = dst;
+    s->blocked = enable;
+    if (enable) {
+        s->tile[0] = lbmx::kBlk;
+        s->tile[1] = s->tile[2] = 1;
+    }
+    clear_cache(s);
+    return LBM_OK;
+}
+
 lbm_status lbm_set_tile(lbm_sim s, int32_t tx, int32_t ty, int32_t tz) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     const int t[3] = {tx, ty, tz};
     if (!lbmx::step_tile_supported(s->d.dtype, s->d.dim, t))
         return fail(LBM_EUNSUPPORTED, "tile %dx%dx%d not compiled for dim %d", tx, ty, tz, s->d.dim);
+    if (s->blocked && (tx != lbmx::kBlk || ty != 1 || tz != 1))
+        return fail(LBM_EUNSUPPORTED, "the blocked population order runs with tile %dx1x1 only", lbmx::kBlk);
     s->tile[0] = tx;
     s->tile[1] = ty;
     s->tile[2] = tz;

@@ -13,6 +13,11 @@ template <typename P> __device__ __forceinline__ const P *pop(const void *base, 
 template <typename P> __device__ __forceinline__ P *pop_w(void *base, int i, uint32_t N) {
     return reinterpret_cast<P *>(base) + (size_t)i * N;
 }
+// Translational slot i of node x in either value order.
+template <typename P, int D>
+__device__ __forceinline__ P fget(const void *base, int blocked, uint32_t N, int i, uint32_t x) {
+    return reinterpret_cast<const P *>(base)[pop_index(blocked, Lat<D>::Q, N, i, x)];
+}
 
 // Fixed-order workgroup reduction of K doubles; thread 0 writes dst[0..K-1].
 template <int NT, int K>
@@ -47,7 +52,7 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_init(InitA
     const FeqCoef<double> fc = feq_coef<double, D>(a.rho[x], uu, a.T[x]);
     static_for<0, Lat<D>::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        pop_w<P>(a.f, i, a.N)[x] = (P)feq_dir<double, D, i>(fc);
+        reinterpret_cast<P *>(a.f)[pop_index(a.blocked, Lat<D>::Q, a.N, i, x)] = (P)feq_dir<double, D, i>(fc);
     });
     const GeqCoef<double> gc = geq_coef<double>(a.T[x]);
     static_for<0, 7>([&](auto J) {
@@ -80,7 +85,8 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_fields(Fie
     const int shift = a.layout == kLayoutStreamed ? 0 : 1;
     Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
     for (int i = 0; i < Lat<D>::Q; ++i) {
-        const double v = (double)pop<P>(a.f, src_slot<D>(a, i), a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
+        const double v = (double)fget<P, D>(a.f, a.blocked, a.N, src_slot<D>(a, i),
+                                            src_index<D>(a, cx, cy, cz, i, shift));
         M.m0 += v;
         M.m1[0] += cx_of(i) * v;
         if (D >= 2) M.m1[1] += cy_of(i) * v;
@@ -123,9 +129,22 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_export(Fie
     if (a.f_out)
         for (int i = 0; i < Lat<D>::Q; ++i)
             pop_w<P>(a.f_out, i, a.N)[x] =
-                pop<P>(a.f, src_slot<D>(a, i), a.N)[src_index<D>(a, cx, cy, cz, i, shift)];
+                fget<P, D>(a.f, a.blocked, a.N, src_slot<D>(a, i), src_index<D>(a, cx, cy, cz, i, shift));
     if (a.g_out)
         for (int j = 0; j < 7; ++j) pop_w<P>(a.g_out, j, a.N)[x] = pop<P>(a.g, j, a.N)[x];
+}
+
+// dst (blocked) <- src (plain); one thread per element of dst, read side
+// gathered.
+template <typename P>
+__global__ void __launch_bounds__(256) k_to_blocked(int Q, uint32_t N, const P *src, P *dst) {
+    const size_t e = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (e >= (size_t)Q * N) return;
+    const uint32_t lane = (uint32_t)(e % kBlk);
+    const size_t bq = e / kBlk;
+    const int i = (int)(bq % Q);
+    const uint32_t x = (uint32_t)(bq / Q) * kBlk + lane;
+    dst[e] = src[(size_t)i * N + x];
 }
 
 __global__ void __launch_bounds__(256) k_reduce(const double *partials, int nparts, int K,
@@ -149,6 +168,17 @@ __global__ void __launch_bounds__(256) k_reduce(const double *partials, int npar
 // Launchers
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(uint32_t N) { return (N + 255u) / 256u; }
+
+hipError_t launch_to_blocked(int dtype, int Q, uint32_t N, const void *src, void *dst, hipStream_t s) {
+    if (N % kBlk) return hipErrorInvalidValue;
+    const size_t n = (size_t)Q * N;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_to_blocked<float>, g, b, 0, s, Q, N, (const float *)src, (float *)dst);
+    else
+        hipLaunchKernelGGL(k_to_blocked<double>, g, b, 0, s, Q, N, (const double *)src, (double *)dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(int dtype, int dim, const InitArgs &a, hipStream_t s) {
     const dim3 g(blocks_for(a.N)), b(256);

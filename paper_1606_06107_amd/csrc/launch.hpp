@@ -20,6 +20,16 @@ enum { kLayoutPost = 0, kLayoutStreamed = 1, kLayoutSwapped = 2 };
 // the same set of locations, so nodes never conflict).
 enum { kSchemePingPong = 0, kSchemeInPlaceEven = 1, kSchemeInPlaceOdd = 2 };
 
+// Order of the values inside a translational buffer.  Plain: slot i of node
+// x at i*N + x.  Blocked (3-D grids with n0 a multiple of 64): the nodes form
+// blocks of 64 x-consecutive nodes (block b = x/64 in linear node order) and
+// slot i of node x sits at ((x/64)*Q + i)*64 + x%64, so a block's populations
+// are one contiguous run.  Rotational buffers are always plain.
+constexpr int kBlk = 64;
+__host__ __device__ inline size_t pop_index(int blocked, int Q, uint32_t N, int i, uint32_t x) {
+    return blocked ? ((size_t)(x / kBlk) * Q + i) * kBlk + x % kBlk : (size_t)i * N + x;
+}
+
 // Arguments of the per-step kernels (one time step of Sec. V B).
 struct StepArgs {
     const void *f_in;   // [Q][N] translational populations (see `layout`)
@@ -31,6 +41,7 @@ struct StepArgs {
     uint32_t N;         // n0*n1*n2
     int layout;         // kLayout* of f_in
     int scheme;         // kScheme*
+    int blocked;        // value order of f_in / f_out (3-D only)
     double omega;       // 1/tau
     double n_rot;       // rotational degrees of freedom
     double *partials;   // NULL, or [ntiles][2+D] FP64 per-tile totals of time t
@@ -44,6 +55,7 @@ struct FieldArgs {
     int n0, n1, n2, open0, open1, open2;
     uint32_t N;
     int layout;         // kLayout* of f
+    int blocked;        // value order of f (f_out is always plain)
     double n_rot;
     double *rho, *u, *T;  // any may be NULL
     double *partials;     // NULL or [nblocks][2+D]
@@ -59,7 +71,11 @@ struct InitArgs {
     const double *rho, *u, *T;
     void *f, *g;
     uint32_t N;
+    int blocked;        // value order of f
 };
+
+// Copy plain populations src[Q][N] into dst in blocked order.
+hipError_t launch_to_blocked(int dtype, int Q, uint32_t N, const void *src, void *dst, hipStream_t s);
 
 hipError_t launch_init(int dtype, int dim, const InitArgs &a, hipStream_t s);
 // Message returned by lbm_last_error() on this thread.

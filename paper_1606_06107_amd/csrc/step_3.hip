@@ -8,11 +8,17 @@ namespace lbmx {
 hipError_t launch_step_3(int dtype, const int tile[3], const StepArgs &a, hipStream_t s) {
     const dim3 grid(a.ntiles);
     bool done = false;
-#define L3(TXv, TYv)                                                                      \
-    if (!done && tile[0] == TXv && tile[1] == TYv) {                                      \
-        if (dtype == 0) hipLaunchKernelGGL((k_step_3<float, TXv, TYv>), grid, dim3(256), 0, s, a); \
-        else hipLaunchKernelGGL((k_step_3<double, TXv, TYv>), grid, dim3(256), 0, s, a);  \
-        done = true;                                                                      \
+    if (a.blocked) {  // one 64-node block per tile
+        if (tile[0] != kBlk || tile[1] != 1 || a.n0 % kBlk) return hipErrorInvalidValue;
+        if (dtype == 0) hipLaunchKernelGGL((k_step_3<float, kBlk, 1, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_step_3<double, kBlk, 1, true>), grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+#define L3(TXv, TYv)                                                                             \
+    if (!done && tile[0] == TXv && tile[1] == TYv) {                                             \
+        if (dtype == 0) hipLaunchKernelGGL((k_step_3<float, TXv, TYv, false>), grid, dim3(256), 0, s, a); \
+        else hipLaunchKernelGGL((k_step_3<double, TXv, TYv, false>), grid, dim3(256), 0, s, a);  \
+        done = true;                                                                             \
     }
     LBMX_TILES_3D(L3)
 #undef L3

@@ -428,11 +428,20 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
 constexpr int kQ3 = 343;
 constexpr int kSplit3 = 86;  // populations per wave: 86, 86, 86, 85
 
-template <typename P, int W>
+// Blocked value order (pop_index): the 64 nodes of a tile are one block, and
+// the block of every source row starts at a uniform address.  Byte offsets:
+struct Blk3 {
+    uint32_t lo[7];        // lane's source within its row, per cx + 3
+    size_t yb[7], zb[7];   // source row part, per cy + 3 and cz + 3
+    size_t ob;             // the tile's own block
+    uint32_t row_bytes;    // one row of blocks (n0 / 64 blocks)
+};
+
+template <typename P, int W, bool BLK>
 __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7], const int (&sy)[7],
-                                           const int (&sz)[7], uint32_t node, int xc, int yc,
-                                           int zc, bool valid, int tile, double (*part)[64][6],
-                                           double (*part2)[64][8]) {
+                                           const int (&sz)[7], const Blk3 &B, uint32_t node, int xc,
+                                           int yc, int zc, bool valid, int tile,
+                                           double (*part)[64][6], double (*part2)[64][8]) {
     constexpr int LO = W * kSplit3;
     constexpr int HI = (W + 1) * kSplit3 < kQ3 ? (W + 1) * kSplit3 : kQ3;
     constexpr bool F32 = sizeof(P) == 4;
@@ -442,8 +451,16 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
     double m0 = 0.0, mx = 0.0, my = 0.0, mz = 0.0, e2 = 0.0, er = 0.0;
     static_for<LO, HI>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        const uint32_t idx = (uint32_t)(sx[cx_of(i) + 3] + sy[cy_of(i) + 3] + sz[cz_of(i) + 3]);
-        const P f = ldp_stream<P>(a.f_in, i, N, idx * (uint32_t)sizeof(P));
+        P f;
+        if constexpr (BLK) {
+            const char *row = reinterpret_cast<const char *>(a.f_in) + B.zb[cz_of(i) + 3] + B.yb[cy_of(i) + 3];
+            const __amdgpu_buffer_rsrc_t r =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(row), 0, (int)B.row_bytes, kRsrcWord3);
+            f = ld_buf<P, kCpolLoadStream>(r, B.lo[cx_of(i) + 3], (uint32_t)(i * kBlk * sizeof(P)));
+        } else {
+            const uint32_t idx = (uint32_t)(sx[cx_of(i) + 3] + sy[cy_of(i) + 3] + sz[cz_of(i) + 3]);
+            f = ldp_stream<P>(a.f_in, i, N, idx * (uint32_t)sizeof(P));
+        }
         fv[i - LO] = f;
         const double v = (double)f;
         m0 += v;
@@ -527,6 +544,16 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
     // LDS and the defects go to the special populations (eps_from_defects).
     constexpr int NSP = 7;
     P dsp[NSP];
+    __amdgpu_buffer_rsrc_t out_r;
+    if constexpr (BLK)
+        out_r = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<char *>(a.f_out) + B.ob, 0,
+                                                  (int)(kQ3 * kBlk * sizeof(P)), kRsrcWord3);
+    auto store_f = [&](int i, P v) {
+        if constexpr (BLK)
+            st_buf<P, kCpolStoreStream>(out_r, (uint32_t)(lane * sizeof(P)), (uint32_t)(i * kBlk * sizeof(P)), v);
+        else
+            stp_stream<P>(a.f_out, i, N, node * (uint32_t)sizeof(P), v);
+    };
     P s0 = P(0), s1x = P(0), s1y = P(0), s1z = P(0), s2 = P(0);
     static_for<LO, HI>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -540,7 +567,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
             if constexpr (c2_of<3>(i) != 0) s2 += P(c2_of<3>(i)) * d;
         }
         if constexpr (F32 && sr >= 0) dsp[sr] = d;
-        else if (valid) stp_stream<P>(a.f_out, i, N, node * (uint32_t)sizeof(P), fv[i - LO] + d);
+        else if (valid) store_f(i, fv[i - LO] + d);
     });
     P gal = P(0), gga = P(0);
     if constexpr (F32) {
@@ -574,7 +601,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
             constexpr int i = decltype(I)::value;
             constexpr int sr = special_rank<3>(i);
             if constexpr (sr >= 0)
-                if (valid) stp_stream<P>(a.f_out, i, N, node * (uint32_t)sizeof(P), fv[i - LO] + (dsp[sr] + (P)ep.e[sr]));
+                if (valid) store_f(i, fv[i - LO] + (dsp[sr] + (P)ep.e[sr]));
         });
         double ga_d, ga_g;
         gfix_from_defects(a.omega * (1.0 - S[7]) - S[5], a.omega * (T * kInvR2 - M.er) - S[6],
@@ -595,8 +622,9 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
     if constexpr (HAS1) relax_store(Int<J1 < 7 ? J1 : 0>{}, g1, adv1);
 }
 
-template <typename P, int TX, int TY>
+template <typename P, int TX, int TY, bool BLK>
 __global__ void __launch_bounds__(256) k_step_3(StepArgs a) {
+    static_assert(!BLK || (TX == kBlk && TY == 1), "blocked order: one block per tile");
     static_assert(TX * TY == 64, "64 nodes per workgroup");
     __shared__ double part[4][64][6];
     __shared__ double part2[4][64][8];
@@ -616,11 +644,25 @@ __global__ void __launch_bounds__(256) k_step_3(StepArgs a) {
         sy[k] = nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * a.n0;
         sz[k] = nb_coord(zc, -(k - 3) * shift, a.n2, a.open2) * (a.n0 * a.n1);
     }
+    Blk3 B;
+    if constexpr (BLK) {  // n0 % 64 == 0: the tile is block t0 of row (y, z)
+        const size_t blk_bytes = (size_t)kQ3 * kBlk * sizeof(P);
+        const uint32_t tpr = (uint32_t)a.n0 / kBlk;
+        B.row_bytes = (uint32_t)(tpr * blk_bytes);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const uint32_t xs = (uint32_t)sx[k];
+            B.lo[k] = (uint32_t)((xs / kBlk) * blk_bytes + (xs % kBlk) * sizeof(P));
+            B.yb[k] = (size_t)nb_coord(yc, -(k - 3) * shift, a.n1, a.open1) * B.row_bytes;
+            B.zb[k] = (size_t)nb_coord(zc, -(k - 3) * shift, a.n2, a.open2) * a.n1 * B.row_bytes;
+        }
+        B.ob = ((size_t)t0 + (size_t)tpr * ((size_t)yc + (size_t)a.n1 * zc)) * blk_bytes;
+    }
     switch (w) {  // wave-uniform
-        case 0: step3_wave<P, 0>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
-        case 1: step3_wave<P, 1>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
-        case 2: step3_wave<P, 2>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
-        default: step3_wave<P, 3>(a, sx, sy, sz, node, xc, yc, zc, valid, tile, part, part2); break;
+        case 0: step3_wave<P, 0, BLK>(a, sx, sy, sz, B, node, xc, yc, zc, valid, tile, part, part2); break;
+        case 1: step3_wave<P, 1, BLK>(a, sx, sy, sz, B, node, xc, yc, zc, valid, tile, part, part2); break;
+        case 2: step3_wave<P, 2, BLK>(a, sx, sy, sz, B, node, xc, yc, zc, valid, tile, part, part2); break;
+        default: step3_wave<P, 3, BLK>(a, sx, sy, sz, B, node, xc, yc, zc, valid, tile, part, part2); break;
     }
 }
 

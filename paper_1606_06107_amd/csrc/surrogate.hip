@@ -229,14 +229,35 @@ __global__ void __launch_bounds__(256) k_wgrad(WgArgs g) {
     }
 }
 
-// out[j] (= or +=) sum_c part[c][j], c in order.
-__global__ void __launch_bounds__(256) k_reduce_parts(const float *part, int nch, int len, float *out,
-                                                      int accumulate) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= len) return;
+// out[j] (= or +=) sum_c part[c][j] in a fixed order: thread group k of a
+// workgroup sums the chunks c = k (mod 16) in ascending order, then the 16
+// group sums are added in group order.  A workgroup covers 64 outputs.
+constexpr int RED_J = 64, RED_K = 16;
+__global__ void __launch_bounds__(RED_J * RED_K) k_reduce_parts(const float *part, int nch, int len, float *out,
+                                                              int accumulate) {
+    __shared__ float red[RED_K][RED_J];
+    const int jl = threadIdx.x % RED_J, k = threadIdx.x / RED_J;
+    const int j = blockIdx.x * RED_J + jl;
     float s = 0.0f;
-    for (int c = 0; c < nch; ++c) s += part[(size_t)c * len + j];
-    out[j] = accumulate ? out[j] + s : s;
+    if (j < len) {
+        int c = k;
+        for (; c + 3 * RED_K < nch; c += 4 * RED_K) {  // four loads in flight, same order
+            const float v0 = part[(size_t)c * len + j], v1 = part[(size_t)(c + RED_K) * len + j];
+            const float v2 = part[(size_t)(c + 2 * RED_K) * len + j], v3 = part[(size_t)(c + 3 * RED_K) * len + j];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; c < nch; c += RED_K) s += part[(size_t)c * len + j];
+    }
+    red[k][jl] = s;
+    __syncthreads();
+    if (k == 0 && j < len) {
+        float t = red[0][jl];
+        for (int q = 1; q < RED_K; ++q) t += red[q][jl];
+        out[j] = accumulate ? out[j] + t : t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -341,10 +362,16 @@ __global__ void __launch_bounds__(256) k_loss(Shape s, const double *x, const do
 }
 
 __global__ void __launch_bounds__(256) k_loss_final(const float *lpart, int n, int count, float *loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ float red[256];
     float s = 0.0f;
-    for (int i = 0; i < n; ++i) s += lpart[i];
-    *loss = s / (float)count;
+    for (int i = threadIdx.x; i < n; i += 256) s += lpart[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / (float)count;
 }
 
 // [c][6] partial sums -> kc[c][5], bc[c] gradients
@@ -751,6 +778,7 @@ lbm_status svalidate(const lbm_sur_desc *d) {
 }
 
 unsigned nblk(size_t n) { return (unsigned)((n + 255) / 256); }
+unsigned nred(size_t n) { return (unsigned)((n + RED_J - 1) / RED_J); }
 
 template <int N, int K, bool AF32, int EPI>
 void gemm(hipStream_t s, int M, int nvalid, const void *A, const __bf16 *Bt, const float *bias,
@@ -765,8 +793,8 @@ void wgrad(hipStream_t s, int M, int Nv, int Kv, const void *A, const void *B, f
     const int nch = (int)nchunk128(M);
     WgArgs g{M, Nv, Kv, A, B, part, gb ? bpart : nullptr};
     hipLaunchKernelGGL((k_wgrad<N, K, NA, KB, AF32, BF32>), dim3(nch), dim3(256), 0, s, g);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk((size_t)Nv * Kv)), dim3(256), 0, s, part, nch, Nv * Kv, gW, 0);
-    if (gb) hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(Nv)), dim3(256), 0, s, bpart, nch, Nv, gb, 0);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nred((size_t)Nv * Kv)), dim3(RED_J * RED_K), 0, s, part, nch, Nv * Kv, gW, 0);
+    if (gb) hipLaunchKernelGGL(k_reduce_parts, dim3(nred(Nv)), dim3(RED_J * RED_K), 0, s, bpart, nch, Nv, gb, 0);
 }
 
 // Forward through the network; keeps every activation needed by backward.
@@ -847,7 +875,7 @@ lbm_status lbm_sur_backward(const lbm_sur_desc *d, const double *x, const double
     const float *P = d->params;
     const unsigned nl = nblk((size_t)M * 16);
     hipLaunchKernelGGL(k_loss, dim3(nl), dim3(256), 0, s, sh, x, target, b.Y, b.dY, b.lpart);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, b.lpart, (int)nl, M * FOUT, loss);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, b.lpart, (int)nl, M * FOUT, loss);
     // head
     wgrad<32, 64, 16, 64, false, true>(s, M, FOUT, C, b.dY, b.H[NB], b.part, b.bpart, grads + P_WH, grads + P_BH);
     gemm<64, 16, false, EPI_F32>(s, M, C, b.dY, Q + Q_WHTP, nullptr, nullptr, b.dH, nullptr, nullptr);
@@ -869,7 +897,7 @@ lbm_status lbm_sur_backward(const lbm_sur_desc *d, const double *x, const double
         const unsigned nc = (unsigned)((M + 63) / 64);
         hipLaunchKernelGGL(k_conv_bwd, dim3(nc), dim3(256), 0, s, sh, b.dHc, b.H[k], blk + B_KC, b.dH, b.part);
         // taps and bias of the convolution: part[wg][c][6] -> [c][6] -> kc, bc
-        hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(C * 6)), dim3(256), 0, s, b.part, (int)nc, C * 6, b.bpart, 0);
+        hipLaunchKernelGGL(k_reduce_parts, dim3(nred(C * 6)), dim3(RED_J * RED_K), 0, s, b.part, (int)nc, C * 6, b.bpart, 0);
         hipLaunchKernelGGL(k_conv_scatter, dim3(1), dim3(64), 0, s, b.bpart, gblk + B_KC, gblk + B_BC);
     }
     wgrad<64, 32, 64, 16, true, false>(s, M, C, FIN, b.dH, b.X, b.part, b.bpart, grads + P_WE, grads + P_BE);

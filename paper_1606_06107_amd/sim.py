@@ -32,8 +32,9 @@ def lattice_info(dim: int):
 
 
 class Sim:
-    """A grid of nodes on one GPU.  Tile, graph and streaming-scheme settings
-    persist across init / init_populations (each creates a new handle).
+    """A grid of nodes on one GPU.  Tile, graph, streaming-scheme and
+    population-order settings persist across init / init_populations (each
+    creates a new handle).
 
     shape: nodes per axis (x first), bc: 'periodic' | 'open' per axis,
     n_rot: rotational degrees of freedom (gamma = (D+n+2)/(D+n)), tau: BGK
@@ -80,8 +81,11 @@ class Sim:
         self._tile = None
         self._graphs = None
         self._inplace = None
+        self._blocked = None
 
     def _apply_settings(self):
+        if self._blocked is not None:  # first: enabling it resets the tile
+            L.check(self.lib.lbm_set_blocked(self.handle, 1 if self._blocked else 0))
         if self._tile is not None:
             L.check(self.lib.lbm_set_tile(self.handle, *[int(v) for v in self._tile]))
         if self._graphs is not None:
@@ -136,6 +140,16 @@ class Sim:
         grids."""
         L.check(self.lib.lbm_set_inplace(self.handle, 1 if on else 0))
         self._inplace = bool(on)
+        return self
+
+    def set_blocked(self, on: bool):
+        """3-D only: populations in blocks of 64 x-consecutive nodes (True) or
+        plain [Q][N] (False); only before the first step.  Default: blocked
+        when n0 is a multiple of 64.  Enabling sets the tile to 64x1x1."""
+        L.check(self.lib.lbm_set_blocked(self.handle, 1 if on else 0))
+        self._blocked = bool(on)
+        if on:
+            self._tile = None
         return self
 
     def set_tile(self, tx, ty=1, tz=1):

@@ -16,7 +16,7 @@ def announce(msg):
 
 
 def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile=None,
-            graphs=True, chunks=None, inplace=None):
+            graphs=True, chunks=None, inplace=None, blocked=None):
     import torch
     from paper_1606_06107_amd import Sim
     sim = Sim(shape, bc=bc, n_rot=n_rot, tau=tau, dtype=dtype).init(*fields)
@@ -25,6 +25,8 @@ def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile
         pf = torch.as_tensor(workloads.nonequilibrium_perturbation(f.shape, perturb_seed)).to(f)
         pg = torch.as_tensor(workloads.nonequilibrium_perturbation(g.shape, perturb_seed + 1)).to(g)
         sim.init_populations(f * pf, g * pg)
+    if blocked is not None:
+        sim.set_blocked(blocked)
     if tile is not None:
         sim.set_tile(*tile)
     if inplace is not None:

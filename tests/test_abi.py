@@ -88,6 +88,8 @@ def test_null_fields_and_handles(lib):
     h = ctypes.c_void_p()
     assert L.lbm_init(ctypes.byref(d), None, None, None, None, ctypes.byref(h)) == lib.LBM_EINVAL
     assert L.lbm_step(None, 1) == lib.LBM_EINVAL
+    assert L.lbm_set_blocked(None, 1) == lib.LBM_EINVAL
+    assert L.lbm_set_inplace(None, 1) == lib.LBM_EINVAL
     assert L.lbm_moments(None, None, None, None, None) == lib.LBM_EINVAL
     assert L.lbm_destroy(None) == lib.LBM_OK
 

@@ -130,6 +130,65 @@ def test_tile_shapes_bitwise_identical(torch_cuda, dim, tiles):
         assert np.array_equal(got["f"], ref["f"]) and np.array_equal(got["g"], ref["g"]), t
 
 
+@pytest.mark.parametrize("shape,bc", [((64, 5, 4), ["periodic", "periodic", "periodic"]),
+                                      ((128, 3, 4), ["open", "periodic", "open"])])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_3d_blocked_order(torch_cuda, shape, bc, dtype):
+    """3-D grids with n0 a multiple of 64 run in the blocked population order
+    by default: parity with the oracle (populations in and out through the
+    reordering import/export), several blocks per row, open and periodic."""
+    announce(f"3-D blocked {dtype} {shape} {bc}")
+    fields = smooth_fields(shape, 6)
+    dt = getattr(torch_cuda, dtype)
+    g = gpu_run(shape, bc, 2.0, 0.7, dt, fields, 6, perturb_seed=9, chunks=[1, 5])
+    o = oracle_run(shape, bc, 2.0, 0.7, fields, 6, perturb_seed=9)
+    if dtype == "float64":
+        _fields_check(g, o, FP64_TOL, "rel")
+        assert rel_err(g["f"], o["f"]) <= FP64_TOL and rel_err(g["g"], o["g"]) <= FP64_TOL
+        assert rel_err(g["tot"], o["tot"]) <= FP64_TOL
+    else:
+        _fields_check(g, o, FP32_TOL, "abs")
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("perturb", [None, 3])
+def test_3d_blocked_equals_plain(torch_cuda, dtype, perturb):
+    """Same arithmetic in both population orders: identical bits after
+    several steps, from lbm_init and from lbm_init_populations."""
+    shape, bc = (64, 6, 5), ["periodic", "open", "periodic"]
+    fields = smooth_fields(shape, 2)
+    dt = getattr(torch_cuda, dtype)
+    announce(f"3-D blocked vs plain {dtype} perturb={perturb}")
+    blk = gpu_run(shape, bc, 2.0, 0.8, dt, fields, 7, perturb_seed=perturb, chunks=[3, 4])
+    pln = gpu_run(shape, bc, 2.0, 0.8, dt, fields, 7, perturb_seed=perturb, chunks=[3, 4], blocked=False,
+                  tile=(16, 4, 1))
+    for k in ("f", "g", "rho", "u", "T", "tot"):
+        assert np.array_equal(blk[k], pln[k]), k
+
+
+def test_3d_blocked_rules(torch_cuda):
+    from paper_1606_06107_amd import Sim
+    from paper_1606_06107_amd._lib import LBM_EINVAL, LBM_EUNSUPPORTED, LbmError
+    announce("3-D blocked rules")
+    fields = smooth_fields((40, 4, 3), 1)
+    sim = Sim((40, 4, 3), tau=0.8).init(*fields)
+    with pytest.raises(LbmError) as e:
+        sim.set_blocked(True)  # n0 not a multiple of 64
+    assert e.value.status == LBM_EUNSUPPORTED
+    fields = smooth_fields((64, 4, 3), 1)
+    sim = Sim((64, 4, 3), tau=0.8).init(*fields)
+    with pytest.raises(LbmError) as e:
+        sim.set_tile(32, 2)  # blocked by default: 64x1 only
+    assert e.value.status == LBM_EUNSUPPORTED
+    sim.set_blocked(False)
+    sim.set_tile(32, 2)
+    sim.set_blocked(True)  # back to blocked; tile reset to 64x1
+    sim.step(1)
+    with pytest.raises(LbmError) as e:
+        sim.set_blocked(False)
+    assert e.value.status == LBM_EINVAL
+
+
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
 @pytest.mark.parametrize("shape", [(200, 40), (37,), (130, 9)])
 def test_inplace_streaming_equals_ping_pong(torch_cuda, dtype, shape):
