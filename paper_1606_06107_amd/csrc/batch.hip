@@ -13,11 +13,12 @@
 // g[0].
 //
 // Work distribution, in two phases of the same launch:
-//  1. long tubes, pass by pass: pass p of every long tube still running is
-//     cut into its chunks and all those chunks are shared by all workgroups;
-//     a grid-wide barrier (a device counter, bounded wait) separates passes.
-//     A single long tube therefore runs on as many compute units as it has
-//     chunks instead of on one: its length no longer sets the launch's time.
+//  1. long tubes, pass by pass: the chunks of every pass of every long tube
+//     are handed out pass-major from one ticket counter and shared by all
+//     workgroups; a chunk of pass p waits only for the chunks of pass p - 1
+//     of its own tube (a per-tube completion count, bounded wait).  A long
+//     tube runs on as many compute units as it has chunks, and a thin pass
+//     leaves no workgroup idle while other tubes have work.
 //  2. tubes that fit on chip, longest work first (a one-workgroup bitonic
 //     sort orders them), popped from a device counter by the persistent
 //     workgroups (list scheduling).
@@ -46,12 +47,12 @@ struct BatchArgs {
     int32_t *status;
     int64_t *steps_done;  // may be NULL
     int32_t *order;     // workspace: on-chip tubes in processing order (nwhole of them)
-    int32_t *counter;   // workspace: [0] queue head, [1] barrier release, [2] abort,
-                        //            [3] nwhole, [4] nlong, [5] chunk tickets,
-                        //            [64 + w] arrival flag of workgroup w
+    int32_t *counter;   // workspace: [0] queue head, [3] nwhole, [4] nlong,
+                        //            [5] chunk tickets
     int32_t *ltube;     // workspace: long tubes, most passes first (nlong)
     int32_t *lpas;      // workspace: their pass counts (non-increasing)
     int32_t *lpfx;      // workspace: prefix sums of their chunk counts (nlong + 1)
+    int32_t *pdone;     // workspace: chunks completed per long tube, all passes (nlong)
     int64_t *fail_at;   // workspace: first failing step of a long tube (INT64_MAX: none)
     int num;
     uint32_t total;
@@ -59,13 +60,14 @@ struct BatchArgs {
     int superstep;  // steps per pass of a chunked tube
 };
 
-constexpr int kCtrQueue = 0, kCtrBarrier = 1, kCtrAbort = 2, kCtrWhole = 3, kCtrLong = 4, kCtrTicket = 5;
-// Arrival flags of the grid barrier, one per workgroup, after the counters.
-constexpr int kFlagBase = 64, kMaxGrid = 1024, kCtrWords = kFlagBase + kMaxGrid;
+constexpr int kCtrQueue = 0, kCtrWhole = 3, kCtrLong = 4, kCtrTicket = 5;
+constexpr int kCtrWords = 64, kMaxGrid = 1024;
 constexpr int64_t kNoFail = 0x7fffffffffffffffLL;
-// Status of long tubes when a grid barrier gave up waiting (never expected:
-// every workgroup of the launch is resident).
+// Status of a long tube whose dependency wait gave up (never expected: the
+// awaited chunks are held by running workgroups).
 constexpr int32_t kStatusAborted = 4;
+// Largest number of chunk tickets of one launch (int32 counts).
+constexpr int64_t kMaxTickets = 1LL << 30;
 
 // Passes of a chunked tube: at most S steps each, at least 2, even.
 __host__ __device__ inline int64_t tube_passes(int64_t steps, int S) {
@@ -81,8 +83,9 @@ __host__ __device__ inline int64_t tube_passes(int64_t steps, int S) {
 // order[0..nwhole); long tubes (L > C) sorted by step count (descending) into
 // ltube[0..nlong) with their pass counts and the prefix sums of their chunk
 // counts.  Bitonic sorts of 64-bit keys (value << 24 | 2^24 - 1 - index) in
-// LDS.  Batches of more than kSortMax tubes keep index order and run every
-// tube in phase 1 (a long tube then walks its chunks on one workgroup).
+// LDS.  Batches of more than kSortMax tubes, or whose long tubes would need
+// more than kMaxTickets chunk passes, keep index order and run every tube in
+// phase 2 (a long tube then walks its chunks on one workgroup).
 // ---------------------------------------------------------------------------
 constexpr int kSortMax = 16384;
 
@@ -113,14 +116,11 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
     const int inner = a.chunk - 6 * a.superstep;
     if (threadIdx.x == 0) {
         a.counter[kCtrQueue] = 0;
-        a.counter[kCtrBarrier] = 0;
-        a.counter[kCtrAbort] = 0;
         a.counter[kCtrTicket] = 0;
         s_cnt[0] = 0;
         s_cnt[1] = 0;
     }
     for (int i = threadIdx.x; i < n; i += 1024) a.fail_at[i] = kNoFail;
-    for (int w = threadIdx.x; w < kMaxGrid; w += 1024) a.counter[kFlagBase + w] = 0;
     if (n > kSortMax) {
         for (int i = threadIdx.x; i < n; i += 1024) a.order[i] = i;
         if (threadIdx.x == 0) {
@@ -197,10 +197,31 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
     int acc = part[threadIdx.x];
     for (int j = threadIdx.x * seg; j < nl && j < (threadIdx.x + 1) * seg; ++j) {
         a.lpfx[j] = acc;
+        a.pdone[j] = 0;
         const int t = a.ltube[j];
         const int64_t L = a.offsets[t + 1] - a.offsets[t];
         acc += (int)((L + inner - 1) / inner);
         a.status[t] = 0;
+    }
+    // total chunk tickets of phase 1 (passes x chunks of every long tube)
+    __shared__ unsigned long long s_tk;
+    if (threadIdx.x == 0) s_tk = 0;
+    __syncthreads();
+    unsigned long long tk = 0;
+    for (int j = threadIdx.x * seg; j < nl && j < (threadIdx.x + 1) * seg; ++j) {
+        const int t = a.ltube[j];
+        const int64_t L = a.offsets[t + 1] - a.offsets[t];
+        const int64_t st = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
+        tk += (unsigned long long)tube_passes(st, a.superstep) * (unsigned long long)((L + inner - 1) / inner);
+    }
+    atomicAdd(&s_tk, tk);
+    __syncthreads();
+    if (s_tk >= (unsigned long long)kMaxTickets) {  // too many: everything in phase 2, index order
+        for (int i = threadIdx.x; i < n; i += 1024) a.order[i] = i;
+        if (threadIdx.x == 0) {
+            a.counter[kCtrWhole] = n;
+            a.counter[kCtrLong] = 0;
+        }
     }
 }
 
@@ -345,83 +366,34 @@ __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, dou
     return cur;
 }
 
-// Grid-wide barrier of a persistent launch whose workgroups are all
-// resident (generation gen = 1, 2, ...).  Each workgroup release-stores gen
-// into its own arrival flag; the first wave of workgroup 0 polls all flags
-// (relaxed device-scope loads, wave-wide minimum) and then release-stores gen
-// into one release word, which the others poll (relaxed; one acquire fence
-// after the wait).  No contended read-modify-write.  Bounded wait: returns
-// false (and sets the abort flag, which every waiter also watches) if the
-// others did not arrive within the bound.
-constexpr long kBarrierSpins = 1L << 24;  // a sleep + a device-scope load each: ~10-30 s
+// Thread 0 of a workgroup: wait until *cnt >= target (relaxed polling with
+// a sleep, then one acquire fence: the awaited chunks' stores are visible to
+// the workgroup after its next barrier), or until the tube has failed
+// (*fail_at set: the chunk will be skipped, nothing to wait for).  Bounded:
+// false after kWaitSpins polls (~10-30 s).
+constexpr long kWaitSpins = 1L << 24;
 
-__device__ bool grid_barrier(int32_t *ctr, int gen) {
-    __shared__ int s_ok;
-    // The workgroup barrier completes every wave's stores (to L2); one
-    // device-scope release by the arriving thread then publishes them (an
-    // L2 write-back per workgroup, not per wave).
-    __syncthreads();
-    const int nwg = (int)gridDim.x;
-    if (blockIdx.x == 0) {
-        if (threadIdx.x < 64) {
-            int ok = 1;
-            long spins = 0;
-            for (;;) {
-                int mn = gen;
-                for (int w = 1 + (int)threadIdx.x; w < nwg; w += 64) {
-                    const int v = __hip_atomic_load(&ctr[kFlagBase + w], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                    mn = v < mn ? v : mn;
-                }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const int o = __shfl_xor(mn, off, 64);
-                    mn = o < mn ? o : mn;
-                }
-                if (mn >= gen) break;  // wave-uniform after the reduction
-                const int ab = __builtin_amdgcn_readfirstlane(
-                    __hip_atomic_load(&ctr[kCtrAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                if (ab) {
-                    ok = 0;
-                    break;
-                }
-                if (++spins > kBarrierSpins) {
-                    if (threadIdx.x == 0)
-                        __hip_atomic_store(&ctr[kCtrAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            if (threadIdx.x == 0) {
-                s_ok = ok;
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");  // others' chunks in, ours out
-                if (ok) __hip_atomic_store(&ctr[kCtrBarrier], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    } else if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&ctr[kFlagBase + blockIdx.x], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1;
-        long spins = 0;
-        while (__hip_atomic_load(&ctr[kCtrBarrier], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-            if (__hip_atomic_load(&ctr[kCtrAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                ok = 0;
-                break;
-            }
-            if (++spins > kBarrierSpins) {
-                __hip_atomic_store(&ctr[kCtrAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other chunks of this pass
-        s_ok = ok;
+__device__ bool wait_count(const int32_t *cnt, int target, const int64_t *fail_at) {
+    long spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(fail_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kNoFail) break;
+        if (++spins > kWaitSpins) return false;
+        __builtin_amdgcn_s_sleep(1);
     }
-    // the acquire above invalidated this CU's caches for every wave
-    __syncthreads();
-    return s_ok != 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+// Long tubes running at pass p (a prefix of ltube: lpas is non-increasing)
+// and the number of chunks of that pass.
+__device__ __forceinline__ int tubes_at_pass(const BatchArgs &a, int nlong, int p) {
+    int lo = 0, hi = nlong;  // first j with lpas[j] <= p
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a.lpas[mid] > p) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // LDS <- rows [0, 7) x nodes [0, R) of f and g starting at packed node
@@ -492,84 +464,83 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
     const uint32_t tot = a.total;
     const int nwhole = a.counter[kCtrWhole];
 
-    // Phase 1: long tubes, pass by pass; the chunks of a pass are shared by
-    // all workgroups, a grid barrier separates passes.  It runs first, so a
-    // barrier only ever waits for one pass of chunk work.
+    // Phase 1: long tubes.  Tickets of one monotonic counter enumerate
+    // (pass, tube, chunk) pass-major, tubes in ltube order.  A chunk of pass
+    // p > 0 first waits until every chunk of pass p - 1 of its tube is done
+    // (pdone): it reads what they wrote and overwrites what they read.  The
+    // awaited chunks have smaller tickets, held by running workgroups, so
+    // every wait ends.  Every ticket counts as done, skipped or not.
     const int nlong = a.counter[kCtrLong];
     const int inner = C - 6 * a.superstep;
     const int maxp = nlong > 0 ? a.lpas[0] : 0;
-    bool ok = true;
-    // Chunks are handed out by tickets from one monotonic counter: pass p
-    // owns tickets [tbase, tbase + items); a workgroup that draws a ticket of
-    // a later pass keeps it until that pass.
-    int tbase = 0, held = -1;
-    for (int p = 0; p < maxp && ok; ++p) {
-        // long tubes still running at pass p: a prefix of the list
-        int lo = 0, hi = nlong;  // first j with lpas[j] <= p
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (a.lpas[mid] > p) lo = mid + 1;
-            else hi = mid;
+    int p = 0, tbase = 0, ntub = 0, items = 0;
+    if (maxp > 0) {
+        ntub = tubes_at_pass(a, nlong, 0);
+        items = a.lpfx[ntub];
+    }
+    while (maxp > 0) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.counter[kCtrTicket], 1);
+        __syncthreads();
+        const int tk = s_item;
+        __syncthreads();
+        while (p < maxp && tk - tbase >= items) {  // this workgroup's tickets only grow
+            tbase += items;
+            if (++p < maxp) {
+                ntub = tubes_at_pass(a, nlong, p);
+                items = a.lpfx[ntub];
+            }
         }
-        const int items = a.lpfx[lo];
-        for (;;) {
-            if (held < 0) {
-                if (threadIdx.x == 0) s_item = atomicAdd(&a.counter[kCtrTicket], 1);
-                __syncthreads();
-                held = s_item;
-                __syncthreads();
+        if (p >= maxp) break;  // uniform: every workgroup leaves phase 1 here
+        const int k = tk - tbase;
+        int jl = 0, jh = ntub - 1;  // last j with lpfx[j] <= k
+        while (jl < jh) {
+            const int mid = (jl + jh + 1) >> 1;
+            if (a.lpfx[mid] <= k) jl = mid;
+            else jh = mid - 1;
+        }
+        const int t = a.ltube[jl];
+        const int nch = a.lpfx[jl + 1] - a.lpfx[jl];
+        const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
+        const int64_t passes = a.lpas[jl];
+        const int64_t done = steps * p / passes;
+        if (threadIdx.x == 0) {
+            const bool ok = p == 0 || wait_count(&a.pdone[jl], p * nch, &a.fail_at[t]);
+            if (!ok) {
+                atomicMax(&a.status[t], kStatusAborted);
+                __hip_atomic_fetch_min(&a.fail_at[t], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (held >= tbase + items) break;  // a later pass's ticket (uniform)
-            const int k = held - tbase;
-            held = -1;
-            int jl = 0, jh = lo - 1;  // last j with lpfx[j] <= k
-            while (jl < jh) {
-                const int mid = (jl + jh + 1) >> 1;
-                if (a.lpfx[mid] <= k) jl = mid;
-                else jh = mid - 1;
-            }
-            const int t = a.ltube[jl];
-            // failed in an earlier pass?  Other workgroups may set fail_at
-            // during this pass: one read per workgroup keeps the branch uniform.
-            if (threadIdx.x == 0) s_item = a.fail_at[t] != kNoFail;
-            __syncthreads();
-            const int skip = s_item;
-            __syncthreads();
-            if (skip) continue;
-            const int64_t base = a.offsets[t];
-            const int L = (int)(a.offsets[t + 1] - base);
-            const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
-            const int64_t passes = a.lpas[jl];
-            const int64_t done = steps * p / passes;
+            // failed in an earlier pass (or earlier in this one)?
+            s_item = !ok || __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kNoFail;
+            s_bad[0] = s_bad[1] = 0;
+        }
+        __syncthreads();
+        if (!s_item) {
             const int sp = (int)(steps * (p + 1) / passes - done);
             const int c0 = (k - a.lpfx[jl]) * inner;
+            const int L = (int)(a.offsets[t + 1] - a.offsets[t]);
             const int c1 = c0 + inner < L ? c0 + inner : L;
             const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
-            if (threadIdx.x == 0) s_bad[0] = s_bad[1] = 0;
-            __syncthreads();
             const int ran = run_chunk<P, B>(F, G, C, reinterpret_cast<const P *>(a.f[p & 1]),
                                             reinterpret_cast<const P *>(a.g[p & 1]),
                                             reinterpret_cast<P *>(a.f[(p + 1) & 1]),
-                                            reinterpret_cast<P *>(a.g[(p + 1) & 1]), tot, base, L, c0, c1, sp,
-                                            (P)omega, omega, n_rot, s_bad);
+                                            reinterpret_cast<P *>(a.g[(p + 1) & 1]), tot, a.offsets[t], L, c0,
+                                            c1, sp, (P)omega, omega, n_rot, s_bad);
             const int fail = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
             if (threadIdx.x == 0 && fail) {
                 atomicMax(&a.status[t], fail);
                 __hip_atomic_fetch_min(&a.fail_at[t], (int64_t)(done + ran), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
-            __syncthreads();
         }
-        tbase += items;
-        ok = grid_barrier(a.counter, p + 1);
-    }
-    // results: steps completed, and the status of an aborted schedule
-    for (int j = blockIdx.x * B + threadIdx.x; j < nlong; j += gridDim.x * B) {
-        const int t = a.ltube[j];
-        if (!ok) a.status[t] = kStatusAborted;
-        if (a.steps_done) {
-            const int64_t f = a.fail_at[t];
-            a.steps_done[t] = f != kNoFail ? f : (a.nsteps[t] > 0 ? a.nsteps[t] : 0);
+        __syncthreads();  // every wave's stores have reached the cache
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const int old = __hip_atomic_fetch_add(&a.pdone[jl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1 == (int)passes * nch && a.steps_done) {  // the tube's last chunk
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const int64_t f = __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                a.steps_done[t] = f != kNoFail ? f : steps;
+            }
         }
     }
 
@@ -717,7 +688,7 @@ lbm_status plan(const lbm_batch_desc *d, Launch *L) {
         if (d->chunk < 64) return bfail(LBM_EINVAL, "chunk must be >= 64");
         if (d->chunk / 64 * 64 < C) C = d->chunk / 64 * 64;
     }
-    const int S = d->superstep ? d->superstep : (d->dtype == LBM_F32 ? 16 : 8);
+    const int S = d->superstep ? d->superstep : (d->dtype == LBM_F32 ? 32 : 16);
     if (C - 6 * S < 64) return bfail(LBM_EINVAL, "superstep too large for the chunk");
     L->block = B;
     L->chunk = C;
@@ -780,7 +751,8 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
     a.ltube = a.order + n;
     a.lpas = a.ltube + n;
     a.lpfx = a.lpas + n;
-    a.fail_at = reinterpret_cast<int64_t *>(a.counter + lbmx::kCtrWords + ((4 * n + 1 + 1) & ~(size_t)1));
+    a.pdone = a.lpfx + n + 1;
+    a.fail_at = reinterpret_cast<int64_t *>(a.counter + lbmx::kCtrWords + ((5 * n + 1 + 1) & ~(size_t)1));
     a.num = (int)d->num_instances;
     a.total = (uint32_t)d->total_nodes;
     a.chunk = L.chunk;
@@ -788,8 +760,8 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
     int dev = 0, cus = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // one resident workgroup per compute unit (the LDS chunk fills it): the
-    // long-tube passes spread a tube's chunks over all of them
+    // one workgroup per compute unit (the LDS chunk fills it): the long-tube
+    // passes spread a tube's chunks over all of them
     const int grid = cus < lbmx::kMaxGrid ? cus : lbmx::kMaxGrid;
     if (!prepare) {
         hipLaunchKernelGGL(lbmx::k_batch_order, dim3(1), dim3(1024), 0, s, a);
@@ -806,10 +778,10 @@ extern "C" {
 
 size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc) {
     if (!desc || desc->num_instances < 1) return 0;
-    // counters and barrier flags [kCtrWords], order, ltube, lpas [n] each,
-    // lpfx [n+1] (int32, padded to 8 bytes), fail_at [n] (int64)
+    // counters [kCtrWords], order, ltube, lpas [n] each, lpfx [n+1], pdone
+    // [n] (int32, padded to 8 bytes), fail_at [n] (int64)
     const size_t n = (size_t)desc->num_instances;
-    const size_t i32 = lbmx::kCtrWords + ((4 * n + 1 + 1) & ~(size_t)1);
+    const size_t i32 = lbmx::kCtrWords + ((5 * n + 1 + 1) & ~(size_t)1);
     return ((i32 * 4 + n * 8 + 255) / 256) * 256;
 }
 
