@@ -210,7 +210,7 @@ typedef struct {
     int32_t block;          /* threads per workgroup: 256, 512 or 1024 (0 = default) */
     int32_t chunk;          /* nodes per on-chip chunk, 0 = largest that fits */
     int32_t superstep;      /* time steps per on-chip pass of a chunked tube
-                               (0 = default: 32 in FP32, 16 in FP64) */
+                               (0 = default: 48 in FP32, 32 in FP64) */
 } lbm_batch_desc;
 
 size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc);

@@ -85,9 +85,10 @@ def tune_sim(sim, steps=20, reps=3, force=False):
     return bt, table
 
 
-def tune_batch(make_batch, blocks=(256, 512, 1024), supersteps=(8, 16, 32), force=False, key_extra=""):
-    """make_batch(block, superstep) -> a freshly initialised Batch; each is
-    stepped once and timed.  Returns ((block, superstep), table)."""
+def tune_batch(make_batch, init_args, blocks=(512, 1024), supersteps=(32, 48, 64), force=False, key_extra=""):
+    """make_batch(block, superstep) -> a Batch; each candidate is stepped once
+    (graph capture), re-initialised from init_args = (rho, u, T) and timed on
+    its second step.  Returns ((block, superstep), table)."""
     _load()
     key = f"batch|{key_extra}|{_arch()}"
     if key in _mem and not force:
@@ -96,6 +97,9 @@ def tune_batch(make_batch, blocks=(256, 512, 1024), supersteps=(8, 16, 32), forc
     for blk in blocks:
         for sup in supersteps:
             b = make_batch(blk, sup)
+            b.init(*init_args)
+            b.step()
+            b.init(*init_args)
             a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             a.record(b.stream)
@@ -103,6 +107,7 @@ def tune_batch(make_batch, blocks=(256, 512, 1024), supersteps=(8, 16, 32), forc
             e.record(b.stream)
             torch.cuda.synchronize()
             table[f"{blk}/{sup}"] = a.elapsed_time(e)
+            del b
     best = min(table, key=table.get)
     bb = tuple(int(v) for v in best.split("/"))
     _mem[key] = {"best": list(bb), "table": table}

@@ -688,7 +688,7 @@ lbm_status plan(const lbm_batch_desc *d, Launch *L) {
         if (d->chunk < 64) return bfail(LBM_EINVAL, "chunk must be >= 64");
         if (d->chunk / 64 * 64 < C) C = d->chunk / 64 * 64;
     }
-    const int S = d->superstep ? d->superstep : (d->dtype == LBM_F32 ? 32 : 16);
+    const int S = d->superstep ? d->superstep : (d->dtype == LBM_F32 ? 48 : 32);
     if (C - 6 * S < 64) return bfail(LBM_EINVAL, "superstep too large for the chunk");
     L->block = B;
     L->chunk = C;
