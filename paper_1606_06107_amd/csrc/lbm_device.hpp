@@ -209,6 +209,10 @@ template <typename P> __device__ __forceinline__ void stp(void *base, int i, uin
 // is ~11 % faster than the default policy.
 constexpr int kCpolLoadStream = 2;    // nt
 constexpr int kCpolStoreStream = 16;  // sc1
+// Rotational populations (always ping-pong) and the blocked 3-D stores, whose
+// whole 87.8 kB block is written in one piece: sc1 + nt measured faster there.
+constexpr int kCpolStoreG = 16;
+constexpr int kCpolStoreBlock = 18;   // sc1 nt
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void *base, int i, uint32_t N,
                                                            uint32_t sz) {
@@ -223,16 +227,15 @@ template <typename P> __device__ __forceinline__ P ldp_stream(const void *base, 
     else
         return __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, kCpolLoadStream));
 }
-template <typename P> __device__ __forceinline__ void stp_stream(void *base, int i, uint32_t N,
-                                                                uint32_t off, P v) {
+template <typename P, int CPOL = kCpolStoreStream>
+__device__ __forceinline__ void stp_stream(void *base, int i, uint32_t N, uint32_t off, P v) {
     const __amdgpu_buffer_rsrc_t r = pop_rsrc(base, i, N, sizeof(P));
     if constexpr (sizeof(P) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
-                                              kCpolStoreStream);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, CPOL);
     else
         __builtin_amdgcn_raw_buffer_store_b64(
             __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r,
-            (int)off, 0, kCpolStoreStream);
+            (int)off, 0, CPOL);
 }
 
 // Equilibrium of the direction pair (c, -c): with a = c.ru,

@@ -136,12 +136,12 @@ __device__ __forceinline__ void rot_relax_store(const P (&gv)[7], const P (&adv)
         static_for<0, 7>([&](auto J) {
             constexpr int j = decltype(J)::value;
             const P fixj = P(kW1[iabs(j - 3)]) * (alp + P((j - 3) * (j - 3)) * gam);
-            st<P>(g_out, j, N, off, gv[j] - adv[j] + (rl[j] + fixj));
+            stp_stream<P, kCpolStoreG>(g_out, j, N, off, gv[j] - adv[j] + (rl[j] + fixj));
         });
     } else {
         static_for<0, 7>([&](auto J) {
             constexpr int j = decltype(J)::value;
-            st<P>(g_out, j, N, off, gv[j] - adv[j] - om * (gv[j] - geq_dir<P, j>(gc)));
+            stp_stream<P, kCpolStoreG>(g_out, j, N, off, gv[j] - adv[j] - om * (gv[j] - geq_dir<P, j>(gc)));
         });
     }
 }
@@ -550,7 +550,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
                                                   (int)(kQ3 * kBlk * sizeof(P)), kRsrcWord3);
     auto store_f = [&](int i, P v) {
         if constexpr (BLK)
-            st_buf<P, kCpolStoreStream>(out_r, (uint32_t)(lane * sizeof(P)), (uint32_t)(i * kBlk * sizeof(P)), v);
+            st_buf<P, kCpolStoreBlock>(out_r, (uint32_t)(lane * sizeof(P)), (uint32_t)(i * kBlk * sizeof(P)), v);
         else
             stp_stream<P>(a.f_out, i, N, node * (uint32_t)sizeof(P), v);
     };
@@ -616,7 +616,7 @@ __device__ __forceinline__ void step3_wave(const StepArgs &a, const int (&sx)[7]
         if constexpr (F32)
             gn = gcen - adv + (rl + P(kW1[iabs(j - 3)]) * (gal + P((j - 3) * (j - 3)) * gga));
         else gn = gcen - adv + rl;
-        if (valid) stp_stream<P>(a.g_out, j, N, node * (uint32_t)sizeof(P), gn);
+        if (valid) stp_stream<P, kCpolStoreG>(a.g_out, j, N, node * (uint32_t)sizeof(P), gn);
     };
     relax_store(Int<J0>{}, g0, adv0);
     if constexpr (HAS1) relax_store(Int<J1 < 7 ? J1 : 0>{}, g1, adv1);
