@@ -201,16 +201,16 @@ typedef struct {
                                f[1] is scratch */
     void *g[2];             /* device [7][total] of dtype: same roles */
     int32_t *status;        /* device [I] out: 0 ok, 1 non-finite, 2 rho<=0 or T<=0,
-                               3 empty tube, 4 not completed (a chunk of a long
-                               tube gave up waiting for the previous pass; not
-                               expected); a failing tube stops at the step
-                               that failed and its state is then unspecified */
+                               3 empty tube, 4 not completed (a bounded wait of
+                               the long-tube work queue gave up; not expected);
+                               a failing tube stops at the step that failed and
+                               its state is then unspecified */
     int64_t *steps_done;    /* device [I] out (may be NULL): steps completed */
     void *workspace;        /* device, lbm_batch_workspace_bytes() bytes */
     int32_t block;          /* threads per workgroup: 256, 512 or 1024 (0 = default) */
     int32_t chunk;          /* nodes per on-chip chunk, 0 = largest that fits */
     int32_t superstep;      /* time steps per on-chip pass of a chunked tube
-                               (0 = default: 48 in FP32, 32 in FP64) */
+                               (0 = default 24) */
 } lbm_batch_desc;
 
 size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc);
@@ -222,13 +222,14 @@ lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const d
 
 /* Advance every tube i by nsteps[i] steps in ONE persistent launch (one
  * workgroup per compute unit).  Tubes longer than one on-chip chunk advance
- * first, in passes of at most `superstep` steps: each pass cuts every such
- * tube into chunks with overlapping halos, all workgroups share the chunks
- * (handed out pass by pass), and a chunk waits only for the previous pass
- * of its own tube.  A workgroup that finds no chunk left takes the tubes
- * that fit on chip, which run their whole time loop there, longest work
- * first from a device queue.  The result is left in f[0], g[0]; status[i]
- * is written by the end of the launch. */
+ * in passes of at most `superstep` steps: each pass cuts such a tube into
+ * chunks with overlapping halos, and the chunks go through a device work
+ * queue shared by all workgroups; the workgroup that completes a tube's
+ * pass queues the next one (a failed tube stops there).  Workgroups that
+ * find the queue empty, and all of them once the long tubes are done, take
+ * the tubes that fit on chip, which run their whole time loop there,
+ * longest work first.  The result is left in f[0], g[0]; status[i] is
+ * written by the end of the launch. */
 lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream);
 
 /* Packed FP64 fields rho[total], u[total], T[total] of the state in f[0], g[0];

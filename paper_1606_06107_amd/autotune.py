@@ -85,7 +85,7 @@ def tune_sim(sim, steps=20, reps=3, force=False):
     return bt, table
 
 
-def tune_batch(make_batch, init_args, blocks=(512, 1024), supersteps=(32, 48, 64), force=False, key_extra=""):
+def tune_batch(make_batch, init_args, blocks=(512, 1024), supersteps=(16, 24, 32), force=False, key_extra=""):
     """make_batch(block, superstep) -> a Batch; each candidate is stepped once
     (graph capture), re-initialised from init_args = (rho, u, T) and timed on
     its second step.  Returns ((block, superstep), table)."""

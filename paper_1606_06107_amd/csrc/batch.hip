@@ -13,15 +13,17 @@
 // g[0].
 //
 // Work distribution, in two phases of the same launch:
-//  1. long tubes, pass by pass: the chunks of every pass of every long tube
-//     are handed out pass-major from one ticket counter and shared by all
-//     workgroups; a chunk of pass p waits only for the chunks of pass p - 1
-//     of its own tube (a per-tube completion count, bounded wait).  A long
-//     tube runs on as many compute units as it has chunks, and a thin pass
-//     leaves no workgroup idle while other tubes have work.
+//  1. long tubes, pass by pass, through a device work queue of chunks: the
+//     chunks of pass 0 of every long tube start in the queue; the workgroup
+//     that completes the last chunk of a tube's pass enqueues the chunks of
+//     its next pass (or finishes the tube: last pass, or a failure).  Any
+//     workgroup takes any queued chunk, so a long tube runs on as many
+//     compute units as it has chunks, no chunk ever waits for another, and a
+//     failed tube stops producing work.
 //  2. tubes that fit on chip, longest work first (a one-workgroup bitonic
-//     sort orders them), popped from a device counter by the persistent
-//     workgroups (list scheduling).
+//     sort orders them), popped from a device counter -- by workgroups that
+//     find the chunk queue empty (all but a few reserved ones) and by every
+//     workgroup once the long tubes are done.
 //
 // Per node and step the arithmetic is that of the per-step kernels (Sec. V
 // B): FP64 moments and temperature, fourth-order Hermite equilibria, BGK
@@ -47,12 +49,17 @@ struct BatchArgs {
     int32_t *status;
     int64_t *steps_done;  // may be NULL
     int32_t *order;     // workspace: on-chip tubes in processing order (nwhole of them)
-    int32_t *counter;   // workspace: [0] queue head, [3] nwhole, [4] nlong,
-                        //            [5] chunk tickets
+    int32_t *counter;   // workspace: see kCtr*
     int32_t *ltube;     // workspace: long tubes, most passes first (nlong)
     int32_t *lpas;      // workspace: their pass counts (non-increasing)
     int32_t *lpfx;      // workspace: prefix sums of their chunk counts (nlong + 1)
     int32_t *pdone;     // workspace: chunks completed per long tube, all passes (nlong)
+    int32_t *tpass;     // workspace: pass whose chunks a long tube has queued (nlong)
+    int32_t *tfail;     // workspace: failure kind of a long tube (nlong)
+    int64_t *qitem;     // workspace: chunk queue slots, (long-tube index << 32) | chunk
+    int64_t *qseq;      // workspace: slot sequence: 2 pos + 1 = item of position pos
+                        //            ready; 2 pos = free for position pos
+    int qcap;           // slots in the queue (twice the chunks of one pass of all long tubes)
     int64_t *fail_at;   // workspace: first failing step of a long tube (INT64_MAX: none)
     int num;
     uint32_t total;
@@ -60,12 +67,17 @@ struct BatchArgs {
     int superstep;  // steps per pass of a chunked tube
 };
 
-constexpr int kCtrQueue = 0, kCtrWhole = 3, kCtrLong = 4, kCtrTicket = 5;
+// counter[]: on-chip tube queue head, chunk queue head and tail, on-chip and
+// long tube counts, long tubes not yet finished.
+constexpr int kCtrQueue = 0, kCtrHead = 1, kCtrTail = 2, kCtrWhole = 3, kCtrLong = 4, kCtrRemain = 5;
 constexpr int kCtrWords = 64, kMaxGrid = 1024;
 constexpr int64_t kNoFail = 0x7fffffffffffffffLL;
-// Status of a long tube whose dependency wait gave up (never expected: the
-// awaited chunks are held by running workgroups).
+// Status of a long tube that did not finish (a bounded wait of the chunk
+// queue gave up; never expected).
 constexpr int32_t kStatusAborted = 4;
+// Workgroups that keep polling the chunk queue instead of taking on-chip
+// tubes while long tubes run (the long tubes' passes are the critical path).
+constexpr int kReserve = 16;
 // Largest number of chunk tickets of one launch (int32 counts).
 constexpr int64_t kMaxTickets = 1LL << 30;
 
@@ -116,7 +128,9 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
     const int inner = a.chunk - 6 * a.superstep;
     if (threadIdx.x == 0) {
         a.counter[kCtrQueue] = 0;
-        a.counter[kCtrTicket] = 0;
+        a.counter[kCtrHead] = 0;
+        a.counter[kCtrTail] = 0;
+        a.counter[kCtrRemain] = 0;
         s_cnt[0] = 0;
         s_cnt[1] = 0;
     }
@@ -198,10 +212,13 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
     for (int j = threadIdx.x * seg; j < nl && j < (threadIdx.x + 1) * seg; ++j) {
         a.lpfx[j] = acc;
         a.pdone[j] = 0;
+        a.tpass[j] = 0;
+        a.tfail[j] = 0;
         const int t = a.ltube[j];
         const int64_t L = a.offsets[t + 1] - a.offsets[t];
         acc += (int)((L + inner - 1) / inner);
-        a.status[t] = 0;
+        a.status[t] = kStatusAborted;  // until the tube finishes
+        if (a.steps_done) a.steps_done[t] = 0;
     }
     // total chunk tickets of phase 1 (passes x chunks of every long tube)
     __shared__ unsigned long long s_tk;
@@ -222,6 +239,21 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
             a.counter[kCtrWhole] = n;
             a.counter[kCtrLong] = 0;
         }
+        return;
+    }
+    // chunk queue: the chunks of pass 0 of every long tube at positions
+    // [0, lpfx[nl]), in long-tube order; every other slot free
+    const int np0 = a.lpfx[nl];
+    for (int q = threadIdx.x; q < a.qcap; q += 1024) a.qseq[q] = 2 * (int64_t)q;
+    __syncthreads();
+    for (int j = threadIdx.x * seg; j < nl && j < (threadIdx.x + 1) * seg; ++j)
+        for (int q = a.lpfx[j]; q < a.lpfx[j + 1]; ++q) {
+            a.qitem[q] = ((int64_t)j << 32) | (int64_t)(q - a.lpfx[j]);
+            a.qseq[q] = 2 * (int64_t)q + 1;
+        }
+    if (threadIdx.x == 0) {
+        a.counter[kCtrTail] = np0;
+        a.counter[kCtrRemain] = nl;
     }
 }
 
@@ -366,34 +398,65 @@ __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, dou
     return cur;
 }
 
-// Thread 0 of a workgroup: wait until *cnt >= target (relaxed polling with
-// a sleep, then one acquire fence: the awaited chunks' stores are visible to
-// the workgroup after its next barrier), or until the tube has failed
-// (*fail_at set: the chunk will be skipped, nothing to wait for).  Bounded:
-// false after kWaitSpins polls (~10-30 s).
-constexpr long kWaitSpins = 1L << 24;
+// Bounded polls of the chunk queue (a sleep each): an idle workgroup gives up
+// after ~5-15 s without work (the others go on), a pusher's wait for a free
+// slot after ~1e6 polls (never expected: the slot's consumer is a running
+// workgroup).
+constexpr long kIdleSpins = 1L << 22, kSlotSpins = 1L << 20;
 
-__device__ bool wait_count(const int32_t *cnt, int target, const int64_t *fail_at) {
+__device__ __forceinline__ bool wait_seq(const int64_t *seq, int64_t want) {
     long spins = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(fail_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kNoFail) break;
-        if (++spins > kWaitSpins) return false;
+    while (__hip_atomic_load(seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+        if (++spins > kSlotSpins) return false;
         __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
-// Long tubes running at pass p (a prefix of ltube: lpas is non-increasing)
-// and the number of chunks of that pass.
-__device__ __forceinline__ int tubes_at_pass(const BatchArgs &a, int nlong, int p) {
-    int lo = 0, hi = nlong;  // first j with lpas[j] <= p
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a.lpas[mid] > p) lo = mid + 1;
-        else hi = mid;
+// Thread 0: the next piece of work.  1: a queued chunk (*x = long-tube
+// index, *y = chunk); 2: an on-chip tube (*x = its queue position); 0: the
+// long tubes are done (or this workgroup gave up waiting).  Chunk positions
+// are claimed by fetch-and-add once the queue looks non-empty; a claim that
+// lost the race waits for a later push to fill its position, or for the end
+// of the long tubes (then nothing will fill it).
+__device__ int next_work(const BatchArgs &a, int nwhole, bool &p2_open, int *x, int *y) {
+    int32_t *ctr = a.counter;
+    long spins = 0;
+    for (;;) {
+        const int h = __hip_atomic_load(&ctr[kCtrHead], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int tl = __hip_atomic_load(&ctr[kCtrTail], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < tl) {
+            const int q = atomicAdd(&ctr[kCtrHead], 1);
+            const int slot = q % a.qcap;
+            const int64_t want = 2 * (int64_t)q + 1;
+            for (long w = 0;; ++w) {
+                if (__hip_atomic_load(&a.qseq[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) break;
+                if (__hip_atomic_load(&ctr[kCtrRemain], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
+                    w > kIdleSpins)
+                    return 0;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int64_t it = a.qitem[slot];
+            __hip_atomic_store(&a.qseq[slot], 2 * ((int64_t)q + a.qcap), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            *x = (int)(it >> 32);
+            *y = (int)(it & 0xffffffff);
+            return 1;
+        }
+        if (__hip_atomic_load(&ctr[kCtrRemain], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0) return 0;
+        if (p2_open && (int)blockIdx.x >= kReserve) {
+            const int it = atomicAdd(&ctr[kCtrQueue], 1);
+            if (it < nwhole) {
+                *x = it;
+                return 2;
+            }
+            p2_open = false;
+        }
+        if (++spins > kIdleSpins) return 0;
+        __builtin_amdgcn_s_sleep(4);
     }
-    return lo;
 }
 
 // LDS <- rows [0, 7) x nodes [0, R) of f and g starting at packed node
@@ -454,6 +517,98 @@ __device__ int run_chunk(P *F, P *G, int C, const P *fs, const P *gs, P *fd, P *
     return ran;
 }
 
+// One tube of the on-chip queue (queue position `item`): its whole time loop
+// on chip, or, in index-order mode, its passes chunk by chunk on this
+// workgroup.  Writes its status and steps.  s_bad: LDS flags, zero on entry.
+template <typename P, int B>
+__device__ void whole_tube(const BatchArgs &a, int item, P *F, P *G, int C, int *s_bad) {
+    const uint32_t tot = a.total;
+    const int t = a.order[item];
+    const int64_t base = a.offsets[t];
+    const int L = (int)(a.offsets[t + 1] - base);
+    if (L < 1) {  // empty tube: nothing to advance
+        if (threadIdx.x == 0) {
+            a.status[t] = 3;
+            if (a.steps_done) a.steps_done[t] = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
+    const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
+    const P om = (P)omega;
+    int64_t done_total = 0;
+    const P *f0 = reinterpret_cast<const P *>(a.f[0]);
+    const P *g0 = reinterpret_cast<const P *>(a.g[0]);
+
+    if (L <= C) {
+        // whole tube on chip
+        load_region<P, B>(F, G, C, f0, g0, tot, base, L);
+        int shift, ran;
+        const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, s_bad, &shift,
+                                      &ran);
+        done_total = ran;
+        const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+        P *f0w = reinterpret_cast<P *>(a.f[0]);
+        P *g0w = reinterpret_cast<P *>(a.g[0]);
+        // back to streamed form: f(x) = f*(clamp(x - c))
+        for (int e = threadIdx.x; e < 7 * L; e += B) {
+            const int i = e / L, x = e - i * L;
+            int sx = x - (i - 3) * shift;
+            sx = sx < 0 ? 0 : (sx >= L ? L - 1 : sx);
+            f0w[(size_t)i * tot + base + x] = Fr[i * C + sx];
+            g0w[(size_t)i * tot + base + x] = Gr[i * C + x];
+        }
+    } else {
+        // passes of `superstep` steps over halo'd chunks; even pass count
+        const int S0 = a.superstep;
+        int passes = (int)((steps + S0 - 1) / S0);
+        if (passes < 2) passes = 2;
+        if (passes & 1) ++passes;
+        int64_t done = 0;
+        for (int p = 0; p < passes && !(s_bad[0] | s_bad[1]); ++p) {
+            const int sp = (int)((steps - done) / (passes - p));
+            const P *fs = reinterpret_cast<const P *>(a.f[p & 1]);
+            const P *gs = reinterpret_cast<const P *>(a.g[p & 1]);
+            P *fd = reinterpret_cast<P *>(a.f[(p + 1) & 1]);
+            P *gd = reinterpret_cast<P *>(a.g[(p + 1) & 1]);
+            const int halo = 3 * sp;
+            const int inner = C - 2 * halo;  // > 0 by the host's choice of superstep
+            int pass_ran = sp;
+            for (int c0 = 0; c0 < L; c0 += inner) {
+                const int c1 = c0 + inner < L ? c0 + inner : L;
+                const int lo = c0 - halo > 0 ? c0 - halo : 0;
+                const int hi = c1 + halo < L ? c1 + halo : L;
+                const int R = hi - lo;
+                load_region<P, B>(F, G, C, fs, gs, tot, base + lo, R);
+                int shift, ran;
+                const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo,
+                                              s_bad, &shift, &ran);
+                pass_ran = ran < pass_ran ? ran : pass_ran;
+                const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+                const int W = c1 - c0;
+                for (int e = threadIdx.x; e < 7 * W; e += B) {
+                    const int i = e / W, x = (c0 - lo) + (e - i * W);
+                    int sx = x - (i - 3) * shift;
+                    sx = sx < 0 ? 0 : (sx >= R ? R - 1 : sx);
+                    fd[(size_t)i * tot + base + lo + x] = Fr[i * C + sx];
+                    gd[(size_t)i * tot + base + lo + x] = Gr[i * C + x];
+                }
+                __syncthreads();
+            }
+            done_total = done + pass_ran;
+            done += sp;
+            __threadfence();
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        a.status[t] = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
+        if (a.steps_done) a.steps_done[t] = done_total;
+    }
+    __syncthreads();
+}
+
 template <typename P, int B>
 __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -464,59 +619,41 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
     const uint32_t tot = a.total;
     const int nwhole = a.counter[kCtrWhole];
 
-    // Phase 1: long tubes.  Tickets of one monotonic counter enumerate
-    // (pass, tube, chunk) pass-major, tubes in ltube order.  A chunk of pass
-    // p > 0 first waits until every chunk of pass p - 1 of its tube is done
-    // (pdone): it reads what they wrote and overwrites what they read.  The
-    // awaited chunks have smaller tickets, held by running workgroups, so
-    // every wait ends.  Every ticket counts as done, skipped or not.
+    // Phase 1: chunks of the long tubes from the queue; on-chip tubes while
+    // the queue is empty.  Phase 2: the remaining on-chip tubes.
     const int nlong = a.counter[kCtrLong];
     const int inner = C - 6 * a.superstep;
-    const int maxp = nlong > 0 ? a.lpas[0] : 0;
-    int p = 0, tbase = 0, ntub = 0, items = 0;
-    if (maxp > 0) {
-        ntub = tubes_at_pass(a, nlong, 0);
-        items = a.lpfx[ntub];
-    }
-    while (maxp > 0) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&a.counter[kCtrTicket], 1);
-        __syncthreads();
-        const int tk = s_item;
-        __syncthreads();
-        while (p < maxp && tk - tbase >= items) {  // this workgroup's tickets only grow
-            tbase += items;
-            if (++p < maxp) {
-                ntub = tubes_at_pass(a, nlong, p);
-                items = a.lpfx[ntub];
-            }
-        }
-        if (p >= maxp) break;  // uniform: every workgroup leaves phase 1 here
-        const int k = tk - tbase;
-        int jl = 0, jh = ntub - 1;  // last j with lpfx[j] <= k
-        while (jl < jh) {
-            const int mid = (jl + jh + 1) >> 1;
-            if (a.lpfx[mid] <= k) jl = mid;
-            else jh = mid - 1;
-        }
-        const int t = a.ltube[jl];
-        const int nch = a.lpfx[jl + 1] - a.lpfx[jl];
-        const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
-        const int64_t passes = a.lpas[jl];
-        const int64_t done = steps * p / passes;
+    __shared__ int s_kind, s_x, s_y, s_last, s_pos;
+    bool p2_open = true;  // thread 0's view of the on-chip queue
+    while (nlong > 0) {
         if (threadIdx.x == 0) {
-            const bool ok = p == 0 || wait_count(&a.pdone[jl], p * nch, &a.fail_at[t]);
-            if (!ok) {
-                atomicMax(&a.status[t], kStatusAborted);
-                __hip_atomic_fetch_min(&a.fail_at[t], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            // failed in an earlier pass (or earlier in this one)?
-            s_item = !ok || __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kNoFail;
+            int x = 0, y = 0;
+            s_kind = next_work(a, nwhole, p2_open, &x, &y);
+            s_x = x;
+            s_y = y;
             s_bad[0] = s_bad[1] = 0;
         }
         __syncthreads();
+        const int kind = s_kind, jl = s_x, k = s_y;
+        __syncthreads();
+        if (kind == 0) break;  // uniform
+        if (kind == 2) {
+            whole_tube<P, B>(a, jl, F, G, C, s_bad);
+            continue;
+        }
+        // chunk k of the queued pass of long tube jl
+        const int t = a.ltube[jl];
+        const int nch = a.lpfx[jl + 1] - a.lpfx[jl];
+        const int p = __hip_atomic_load(&a.tpass[jl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
+        const int64_t passes = a.lpas[jl];
+        const int64_t done = steps * p / passes;
+        if (threadIdx.x == 0)  // a chunk of this pass failed: the pass is over
+            s_item = __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kNoFail;
+        __syncthreads();
         if (!s_item) {
             const int sp = (int)(steps * (p + 1) / passes - done);
-            const int c0 = (k - a.lpfx[jl]) * inner;
+            const int c0 = k * inner;
             const int L = (int)(a.offsets[t + 1] - a.offsets[t]);
             const int c1 = c0 + inner < L ? c0 + inner : L;
             const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
@@ -527,7 +664,7 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                                             c1, sp, (P)omega, omega, n_rot, s_bad);
             const int fail = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
             if (threadIdx.x == 0 && fail) {
-                atomicMax(&a.status[t], fail);
+                atomicMax(&a.tfail[jl], fail);
                 __hip_atomic_fetch_min(&a.fail_at[t], (int64_t)(done + ran), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -536,16 +673,38 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
         if (threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const int old = __hip_atomic_fetch_add(&a.pdone[jl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (old + 1 == (int)passes * nch && a.steps_done) {  // the tube's last chunk
+            int last = 0;
+            if (old + 1 == (p + 1) * nch) {  // the pass is complete: finish the tube or queue the next pass
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 const int64_t f = __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                a.steps_done[t] = f != kNoFail ? f : steps;
+                if (f != kNoFail || p + 1 >= passes) {
+                    a.status[t] = __hip_atomic_load(&a.tfail[jl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (a.steps_done) a.steps_done[t] = f != kNoFail ? f : steps;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __hip_atomic_fetch_add(&a.counter[kCtrRemain], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    __hip_atomic_store(&a.tpass[jl], p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    s_pos = atomicAdd(&a.counter[kCtrTail], nch);
+                    last = 1;
+                }
+            }
+            s_last = last;
+        }
+        __syncthreads();
+        if (s_last) {  // publish the next pass's chunks
+            for (int c = threadIdx.x; c < nch; c += B) {
+                const int q = s_pos + c, slot = q % a.qcap;
+                if (!wait_seq(&a.qseq[slot], 2 * (int64_t)q)) continue;  // lost: the tube stays unfinished
+                a.qitem[slot] = ((int64_t)jl << 32) | (int64_t)c;
+                __hip_atomic_store(&a.qseq[slot], 2 * (int64_t)q + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+        __syncthreads();
     }
 
-    // Phase 2: tubes from the queue (on-chip ones; every tube when the
-    // schedule kept index order).
+    // Phase 2: the on-chip tubes still queued (every tube when the schedule
+    // kept index order).
     for (;;) {
         if (threadIdx.x == 0) {
             s_item = atomicAdd(&a.counter[kCtrQueue], 1);
@@ -553,93 +712,10 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
         }
         __syncthreads();
         const int item = s_item;
-        if (item >= nwhole) break;  // uniform: every workgroup reaches this exit
-        const int t = a.order[item];
-        const int64_t base = a.offsets[t];
-        const int L = (int)(a.offsets[t + 1] - base);
-        if (L < 1) {  // empty tube: nothing to advance
-            if (threadIdx.x == 0) {
-                a.status[t] = 3;
-                if (a.steps_done) a.steps_done[t] = 0;
-            }
-            __syncthreads();
-            continue;
-        }
-        const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
-        const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
-        const P om = (P)omega;
-        int64_t done_total = 0;
-        const P *f0 = reinterpret_cast<const P *>(a.f[0]);
-        const P *g0 = reinterpret_cast<const P *>(a.g[0]);
-
-        if (L <= C) {
-            // whole tube on chip
-            load_region<P, B>(F, G, C, f0, g0, tot, base, L);
-            int shift, ran;
-            const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, s_bad, &shift,
-                                          &ran);
-            done_total = ran;
-            const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
-            P *f0w = reinterpret_cast<P *>(a.f[0]);
-            P *g0w = reinterpret_cast<P *>(a.g[0]);
-            // back to streamed form: f(x) = f*(clamp(x - c))
-            for (int e = threadIdx.x; e < 7 * L; e += B) {
-                const int i = e / L, x = e - i * L;
-                int sx = x - (i - 3) * shift;
-                sx = sx < 0 ? 0 : (sx >= L ? L - 1 : sx);
-                f0w[(size_t)i * tot + base + x] = Fr[i * C + sx];
-                g0w[(size_t)i * tot + base + x] = Gr[i * C + x];
-            }
-        } else {
-            // passes of `superstep` steps over halo'd chunks; even pass count
-            const int S0 = a.superstep;
-            int passes = (int)((steps + S0 - 1) / S0);
-            if (passes < 2) passes = 2;
-            if (passes & 1) ++passes;
-            int64_t done = 0;
-            for (int p = 0; p < passes && !(s_bad[0] | s_bad[1]); ++p) {
-                const int sp = (int)((steps - done) / (passes - p));
-                const P *fs = reinterpret_cast<const P *>(a.f[p & 1]);
-                const P *gs = reinterpret_cast<const P *>(a.g[p & 1]);
-                P *fd = reinterpret_cast<P *>(a.f[(p + 1) & 1]);
-                P *gd = reinterpret_cast<P *>(a.g[(p + 1) & 1]);
-                const int halo = 3 * sp;
-                const int inner = C - 2 * halo;  // > 0 by the host's choice of superstep
-                int pass_ran = sp;
-                for (int c0 = 0; c0 < L; c0 += inner) {
-                    const int c1 = c0 + inner < L ? c0 + inner : L;
-                    const int lo = c0 - halo > 0 ? c0 - halo : 0;
-                    const int hi = c1 + halo < L ? c1 + halo : L;
-                    const int R = hi - lo;
-                    load_region<P, B>(F, G, C, fs, gs, tot, base + lo, R);
-                    int shift, ran;
-                    const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo,
-                                                  s_bad, &shift, &ran);
-                    pass_ran = ran < pass_ran ? ran : pass_ran;
-                    const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
-                    const int W = c1 - c0;
-                    for (int e = threadIdx.x; e < 7 * W; e += B) {
-                        const int i = e / W, x = (c0 - lo) + (e - i * W);
-                        int sx = x - (i - 3) * shift;
-                        sx = sx < 0 ? 0 : (sx >= R ? R - 1 : sx);
-                        fd[(size_t)i * tot + base + lo + x] = Fr[i * C + sx];
-                        gd[(size_t)i * tot + base + lo + x] = Gr[i * C + x];
-                    }
-                    __syncthreads();
-                }
-                done_total = done + pass_ran;
-                done += sp;
-                __threadfence();
-                __syncthreads();
-            }
-        }
-        if (threadIdx.x == 0) {
-            a.status[t] = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
-            if (a.steps_done) a.steps_done[t] = done_total;
-        }
         __syncthreads();
+        if (item >= nwhole) break;  // uniform: every workgroup reaches this exit
+        whole_tube<P, B>(a, item, F, G, C, s_bad);
     }
-
 }
 
 }  // namespace lbmx
@@ -677,6 +753,13 @@ struct Launch {
     size_t lds;
 };
 
+// Chunk-queue slots: twice the chunks of one pass over all long tubes, for
+// any launch shape (a chunk covers >= 64 nodes, so a tube of L nodes has at
+// most L / 64 + 1 chunks).
+size_t queue_slots(const lbm_batch_desc *d) {
+    return 2 * ((size_t)d->total_nodes / 64 + (size_t)d->num_instances);
+}
+
 // Chunk capacity: the largest multiple of 64 nodes whose two LDS buffers of
 // 14 populations fit the LDS budget (at most `chunk` if given).
 lbm_status plan(const lbm_batch_desc *d, Launch *L) {
@@ -688,7 +771,7 @@ lbm_status plan(const lbm_batch_desc *d, Launch *L) {
         if (d->chunk < 64) return bfail(LBM_EINVAL, "chunk must be >= 64");
         if (d->chunk / 64 * 64 < C) C = d->chunk / 64 * 64;
     }
-    const int S = d->superstep ? d->superstep : (d->dtype == LBM_F32 ? 48 : 32);
+    const int S = d->superstep ? d->superstep : 24;
     if (C - 6 * S < 64) return bfail(LBM_EINVAL, "superstep too large for the chunk");
     L->block = B;
     L->chunk = C;
@@ -752,7 +835,12 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
     a.lpas = a.ltube + n;
     a.lpfx = a.lpas + n;
     a.pdone = a.lpfx + n + 1;
-    a.fail_at = reinterpret_cast<int64_t *>(a.counter + lbmx::kCtrWords + ((5 * n + 1 + 1) & ~(size_t)1));
+    a.tpass = a.pdone + n;
+    a.tfail = a.tpass + n;
+    a.fail_at = reinterpret_cast<int64_t *>(a.counter + lbmx::kCtrWords + ((7 * n + 1 + 1) & ~(size_t)1));
+    a.qcap = (int)queue_slots(d);
+    a.qitem = a.fail_at + n;
+    a.qseq = a.qitem + a.qcap;
     a.num = (int)d->num_instances;
     a.total = (uint32_t)d->total_nodes;
     a.chunk = L.chunk;
@@ -777,12 +865,13 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
 extern "C" {
 
 size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc) {
-    if (!desc || desc->num_instances < 1) return 0;
-    // counters [kCtrWords], order, ltube, lpas [n] each, lpfx [n+1], pdone
-    // [n] (int32, padded to 8 bytes), fail_at [n] (int64)
+    if (!desc || desc->num_instances < 1 || desc->total_nodes < 0) return 0;
+    // counters [kCtrWords], order, ltube, lpas [n] each, lpfx [n+1], pdone,
+    // tpass, tfail [n] each (int32, padded to 8 bytes); fail_at [n], chunk
+    // queue items and sequences [queue_slots] each (int64)
     const size_t n = (size_t)desc->num_instances;
-    const size_t i32 = lbmx::kCtrWords + ((5 * n + 1 + 1) & ~(size_t)1);
-    return ((i32 * 4 + n * 8 + 255) / 256) * 256;
+    const size_t i32 = lbmx::kCtrWords + ((7 * n + 1 + 1) & ~(size_t)1);
+    return ((i32 * 4 + (n + 2 * queue_slots(desc)) * 8 + 255) / 256) * 256;
 }
 
 lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const double *u,
