@@ -55,12 +55,11 @@ struct BatchArgs {
     int32_t *lpfx;      // workspace: prefix sums of their chunk counts (nlong + 1)
     int32_t *pdone;     // workspace: chunks completed per long tube, all passes (nlong)
     int32_t *tpass;     // workspace: pass whose chunks a long tube has queued (nlong)
-    int32_t *tfail;     // workspace: failure kind of a long tube (nlong)
     int64_t *qitem;     // workspace: chunk queue slots, (long-tube index << 32) | chunk
     int64_t *qseq;      // workspace: slot sequence: 2 pos + 1 = item of position pos
                         //            ready; 2 pos = free for position pos
     int qcap;           // slots in the queue (twice the chunks of one pass of all long tubes)
-    int64_t *fail_at;   // workspace: first failing step of a long tube (INT64_MAX: none)
+    int64_t *fail_at;   // workspace: first failure of a long tube, fail_key (INT64_MAX: none)
     int num;
     uint32_t total;
     int chunk;      // nodes per LDS buffer
@@ -72,6 +71,10 @@ struct BatchArgs {
 constexpr int kCtrQueue = 0, kCtrHead = 1, kCtrTail = 2, kCtrWhole = 3, kCtrLong = 4, kCtrRemain = 5;
 constexpr int kCtrWords = 64, kMaxGrid = 1024;
 constexpr int64_t kNoFail = 0x7fffffffffffffffLL;
+// Failure record of a long tube: the smallest key over its chunks wins, i.e.
+// the earliest failing step and, at that step, the most severe kind -- what
+// the whole tube on chip would report.
+__device__ __forceinline__ int64_t fail_key(int64_t step, int kind) { return (step << 8) | (255 - kind); }
 // Status of a long tube that did not finish (a bounded wait of the chunk
 // queue gave up; never expected).
 constexpr int32_t kStatusAborted = 4;
@@ -213,7 +216,6 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
         a.lpfx[j] = acc;
         a.pdone[j] = 0;
         a.tpass[j] = 0;
-        a.tfail[j] = 0;
         const int t = a.ltube[j];
         const int64_t L = a.offsets[t + 1] - a.offsets[t];
         acc += (int)((L + inner - 1) / inner);
@@ -648,8 +650,11 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
         const int64_t steps = a.nsteps[t] > 0 ? a.nsteps[t] : 0;
         const int64_t passes = a.lpas[jl];
         const int64_t done = steps * p / passes;
-        if (threadIdx.x == 0)  // a chunk of this pass failed: the pass is over
-            s_item = __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kNoFail;
+        if (threadIdx.x == 0) {  // failed in an earlier pass?  (A failure in this pass still lets
+                                 // every chunk of the pass run: the earliest step must be found.)
+            const int64_t f = __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_item = f != kNoFail && (f >> 8) <= done;
+        }
         __syncthreads();
         if (!s_item) {
             const int sp = (int)(steps * (p + 1) / passes - done);
@@ -663,11 +668,9 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                                             reinterpret_cast<P *>(a.g[(p + 1) & 1]), tot, a.offsets[t], L, c0,
                                             c1, sp, (P)omega, omega, n_rot, s_bad);
             const int fail = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
-            if (threadIdx.x == 0 && fail) {
-                atomicMax(&a.tfail[jl], fail);
-                __hip_atomic_fetch_min(&a.fail_at[t], (int64_t)(done + ran), __ATOMIC_RELAXED,
+            if (threadIdx.x == 0 && fail)
+                __hip_atomic_fetch_min(&a.fail_at[t], fail_key(done + ran, fail), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-            }
         }
         __syncthreads();  // every wave's stores have reached the cache
         if (threadIdx.x == 0) {
@@ -678,8 +681,8 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 const int64_t f = __hip_atomic_load(&a.fail_at[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (f != kNoFail || p + 1 >= passes) {
-                    a.status[t] = __hip_atomic_load(&a.tfail[jl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (a.steps_done) a.steps_done[t] = f != kNoFail ? f : steps;
+                    a.status[t] = f != kNoFail ? 255 - (int)(f & 255) : 0;
+                    if (a.steps_done) a.steps_done[t] = f != kNoFail ? f >> 8 : steps;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                     __hip_atomic_fetch_add(&a.counter[kCtrRemain], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
@@ -836,8 +839,7 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
     a.lpfx = a.lpas + n;
     a.pdone = a.lpfx + n + 1;
     a.tpass = a.pdone + n;
-    a.tfail = a.tpass + n;
-    a.fail_at = reinterpret_cast<int64_t *>(a.counter + lbmx::kCtrWords + ((7 * n + 1 + 1) & ~(size_t)1));
+    a.fail_at = reinterpret_cast<int64_t *>(a.counter + lbmx::kCtrWords + ((6 * n + 1 + 1) & ~(size_t)1));
     a.qcap = (int)queue_slots(d);
     a.qitem = a.fail_at + n;
     a.qseq = a.qitem + a.qcap;
@@ -867,10 +869,10 @@ extern "C" {
 size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc) {
     if (!desc || desc->num_instances < 1 || desc->total_nodes < 0) return 0;
     // counters [kCtrWords], order, ltube, lpas [n] each, lpfx [n+1], pdone,
-    // tpass, tfail [n] each (int32, padded to 8 bytes); fail_at [n], chunk
-    // queue items and sequences [queue_slots] each (int64)
+    // tpass [n] each (int32, padded to 8 bytes); fail_at [n], chunk queue
+    // items and sequences [queue_slots] each (int64)
     const size_t n = (size_t)desc->num_instances;
-    const size_t i32 = lbmx::kCtrWords + ((7 * n + 1 + 1) & ~(size_t)1);
+    const size_t i32 = lbmx::kCtrWords + ((6 * n + 1 + 1) & ~(size_t)1);
     return ((i32 * 4 + (n + 2 * queue_slots(desc)) * 8 + 255) / 256) * 256;
 }
 

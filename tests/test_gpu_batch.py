@@ -134,3 +134,58 @@ def test_unstable_tube_flagged(torch_cuda):
     torch_cuda.cuda.synchronize()
     st = b.status.cpu().numpy()
     assert st[0] in (1, 2) and st[1] == 0
+
+
+def test_long_tubes_fail_at_the_same_step_as_on_chip(torch_cuda):
+    """Forcing 256-node chunks turns both tubes into multi-chunk, multi-pass
+    work-queue tubes: the diverging one stops at the same step with the same
+    status as in the whole-tube on-chip run, and the stable one ends with the
+    same bits."""
+    from paper_1606_06107_amd import Batch
+    announce("long tube failure step")
+    f1 = workloads.sod_tube(700, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))   # classic Sod: diverges
+    f2 = workloads.sod_tube(700, (1.0, 0.0, 1.0), (0.5, 0.0, 0.5))
+    rho = np.concatenate([f1[0], f2[0]])
+    u = np.concatenate([f1[1][0], f2[1][0]])
+    T = np.concatenate([f1[2], f2[2]])
+    runs = []
+    for chunk, sup in ((0, 0), (256, 8), (448, 24)):
+        b = Batch([700, 700], [4.0, 4.0], [0.8, 0.8], [300, 300], dtype=torch_cuda.float32, chunk=chunk,
+                  superstep=sup).init(rho, u, T)
+        b.step()
+        torch_cuda.cuda.synchronize()
+        runs.append((b.status.cpu().numpy(), b.steps_done.cpu().numpy(), b.split(b.f[0])[1]))
+    (st0, done0, f0), rest = runs[0], runs[1:]
+    assert st0[0] in (1, 2) and st0[1] == 0 and 0 < done0[0] < 300 and done0[1] == 300
+    for st, done, f in rest:
+        assert np.array_equal(st, st0) and np.array_equal(done, done0)
+        assert np.array_equal(f, f0)
+
+
+def test_index_order_mode_beyond_sort_capacity(torch_cuda):
+    """More tubes than the schedule sorts (16384): every tube runs from the
+    queue in index order, a long one walking its chunks on one workgroup."""
+    from paper_1606_06107_amd import Batch
+    announce("index-order mode")
+    rng = np.random.default_rng(11)
+    small = rng.integers(4, 12, 16400)
+    L0, steps0 = 1500, 60
+    lengths = np.concatenate([[L0], small])
+    I = len(lengths)
+    r0, u0, T0 = workloads.sod_tube(L0, (1.0, 0.0, 1.0), (0.5, 0.0, 0.6))
+    rest = int(small.sum())
+    rho = np.concatenate([r0, np.ones(rest)])
+    u = np.concatenate([u0[0], np.zeros(rest)])
+    T = np.concatenate([T0, np.ones(rest)])
+    steps = np.concatenate([[steps0], rng.integers(0, 6, I - 1)])
+    b = Batch(lengths, np.full(I, 2.0), np.full(I, 0.8), steps, dtype=torch_cuda.float32, chunk=512,
+              superstep=16).init(rho, u, T)
+    b.step()
+    torch_cuda.cuda.synchronize()
+    assert (b.status.cpu().numpy() == 0).all()
+    assert np.array_equal(b.steps_done.cpu().numpy(), steps)
+    R, U, TT = (b.split(x) for x in b.moments())
+    ro, uo, To = _oracle_tube((r0, u0, T0), 2.0, 0.8, steps0)
+    for a_, b_ in ((R[0], ro), (U[0], uo[0]), (TT[0], To)):
+        assert np.abs(a_ - b_).max() <= 1e-5
+    assert max(np.abs(R[i] - 1.0).max() for i in range(1, I, 997)) < 1e-6
