@@ -81,7 +81,8 @@ constexpr int32_t kStatusAborted = 4;
 // Workgroups that keep polling the chunk queue instead of taking on-chip
 // tubes while long tubes run (the long tubes' passes are the critical path).
 constexpr int kReserve = 16;
-// Largest number of chunk tickets of one launch (int32 counts).
+// Largest number of chunk passes (passes x chunks over all long tubes) of one
+// launch: queue positions and completion counts are int32.
 constexpr int64_t kMaxTickets = 1LL << 30;
 
 // Passes of a chunked tube: at most S steps each, at least 2, even.
@@ -93,11 +94,11 @@ __host__ __device__ inline int64_t tube_passes(int64_t steps, int S) {
 }
 
 // ---------------------------------------------------------------------------
-// Schedule (one workgroup): resets the queue head, the barrier and abort
-// flags; on-chip tubes sorted by work (length x steps, descending) into
-// order[0..nwhole); long tubes (L > C) sorted by step count (descending) into
-// ltube[0..nlong) with their pass counts and the prefix sums of their chunk
-// counts.  Bitonic sorts of 64-bit keys (value << 24 | 2^24 - 1 - index) in
+// Schedule (one workgroup): resets the queue counters; on-chip tubes sorted
+// by work (length x steps, descending) into order[0..nwhole); long tubes
+// (L > C) sorted by step count (descending) into ltube[0..nlong) with their
+// pass counts and the prefix sums of their chunk counts, and the chunks of
+// their pass 0 placed in the chunk queue.  Bitonic sorts of 64-bit keys (value << 24 | 2^24 - 1 - index) in
 // LDS.  Batches of more than kSortMax tubes, or whose long tubes would need
 // more than kMaxTickets chunk passes, keep index order and run every tube in
 // phase 2 (a long tube then walks its chunks on one workgroup).
@@ -222,7 +223,7 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
         a.status[t] = kStatusAborted;  // until the tube finishes
         if (a.steps_done) a.steps_done[t] = 0;
     }
-    // total chunk tickets of phase 1 (passes x chunks of every long tube)
+    // chunk passes of phase 1 (passes x chunks of every long tube)
     __shared__ unsigned long long s_tk;
     if (threadIdx.x == 0) s_tk = 0;
     __syncthreads();
