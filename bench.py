@@ -154,6 +154,54 @@ def extra_3d(steps=10):
             "plain_order_ms_per_step": round(ms_plain, 3)}
 
 
+def extra_d2q37(steps=200):
+    """The paper's own 2-D lattice (D2Q37 of Table I) on the 1024^2 periodic
+    workload, FP32, in place, autotuned tile; and the Sec. VI tube
+    (1000 x 16, FP64, 180 steps) as a timing of the paper's experiment."""
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    from paper_1606_06107_amd.autotune import tune_sim
+    w = workloads.Periodic2D()
+    sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32, lattice="D2Q37").init(*w.fields())
+    tile, _ = tune_sim(sim, steps=20, reps=2)
+    sim.init(*w.fields())
+    sim.step(steps)  # capture + warm
+    a, b = _events(sim.stream)
+    torch.cuda.synchronize()
+    a.record(sim.stream)
+    sim.step(steps)
+    b.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    N = w.nx * w.ny
+    gbs = N * 2 * (37 + 7) * 4 / (ms * 1e-3) / 1e9
+    T = sim.moments(totals=False)[2]
+    ok = bool(torch.isfinite(T).all().item())
+    del sim, T
+    # Sec. VI tube: 1000 x 16, open in x, periodic in y, rho 4:1 at T = 1
+    import numpy as np
+    Nx, ny, st = 1000, 16, 180
+    x = (np.arange(Nx) + 0.5) / Nx
+    rho = np.tile(np.where(x < 0.5, 4.0, 1.0), ny)
+    tube = Sim((Nx, ny), bc=["open", "periodic"], n_rot=3.0, tau=2.0 / 3.0, dtype=torch.float64,
+               lattice="D2Q37")
+    tube.init(rho, np.zeros((2, Nx * ny)), np.ones(Nx * ny)).step(st)  # capture + warm
+    tube.init(rho, np.zeros((2, Nx * ny)), np.ones(Nx * ny))
+    a, b = _events(tube.stream)
+    torch.cuda.synchronize()
+    a.record(tube.stream)
+    tube.step(st)
+    b.record(tube.stream)
+    torch.cuda.synchronize()
+    ms_tube = a.elapsed_time(b)
+    return {"workload": "2-D periodic 1024x1024, D2Q37 (Table I) + D1Q7 FP32, in place, same fields as the headline",
+            "tile": list(tile[:2]), "ms_per_step": round(ms, 4), "MLUPS": round(N / ms / 1e3, 1),
+            "GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok,
+            "sec6_tube_1000x16_fp64_180_steps_ms": round(ms_tube, 3)}
+
+
 def extra_batch(seed=0):
     """4096 ragged shock tubes, one persistent launch, FP32 and FP64, with the
     per-instance FP32-vs-FP64 relative L1 error of rho, u, T (Sec. VI)."""
@@ -285,7 +333,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,batched_tubes,surrogate",
+    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,d2q37,batched_tubes,surrogate",
                     help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ping-pong", action="store_true",
@@ -391,7 +439,7 @@ def main():
     if not args.no_extras:
         extra = {}
         wanted = set(args.extras.split(","))
-        for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d),
+        for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d), ("d2q37", extra_d2q37),
                          ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
             if name not in wanted:
                 continue

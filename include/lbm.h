@@ -57,8 +57,10 @@ enum {
     LBM_ELAUNCH = 5       /* kernel launch or graph error */
 };
 
-/* Translational lattices (Table II and its tensor powers). */
-enum { LBM_D1Q7 = 1, LBM_D2Q49 = 2, LBM_D3Q343 = 3 };
+/* Translational lattices: D1Q7 (Table II) and its tensor powers, and the
+ * D2Q37 set of Table I (the D2Q49 velocities without the groups (2r,2r) and
+ * (3r,2r), one weight per group, at the D1Q7 r; dim 2). */
+enum { LBM_D1Q7 = 1, LBM_D2Q49 = 2, LBM_D3Q343 = 3, LBM_D2Q37 = 4 };
 /* Population storage type. */
 enum { LBM_F32 = 0, LBM_F64 = 1 };
 /* Boundary condition per axis: periodic wrap, or open (zero-gradient clamp
@@ -71,7 +73,8 @@ typedef struct {
     int32_t dim;         /* spatial dimension D: 1, 2 or 3 (must match lattice) */
     int64_t n[3];        /* nodes per axis; unused axes must be 1.  Periodic axes
                             need n >= 3; N = n0*n1*n2 with N * sizeof(pop) < 2^32 */
-    int32_t lattice;     /* LBM_D1Q7, LBM_D2Q49 or LBM_D3Q343 */
+    int32_t lattice;     /* LBM_D1Q7 (dim 1), LBM_D2Q49 or LBM_D2Q37 (dim 2),
+                            LBM_D3Q343 (dim 3); Q = 7, 49, 37, 343 */
     int32_t dtype;       /* LBM_F32 or LBM_F64 population storage */
     int32_t bc[3];       /* LBM_BC_PERIODIC or LBM_BC_OPEN per axis */
     double n_rot;        /* rotational degrees of freedom n >= 0 (real);
@@ -177,7 +180,9 @@ lbm_status lbm_destroy(lbm_sim sim);
 const char *lbm_last_error(void);
 
 /* Lattice constants the library computes with: Q, r, and (if not NULL) the
- * weights w[Q] and velocities c[Q][3] (integers).  Host pointers. */
+ * weights w[Q] and velocities c[Q][3] (integers) of the population slots in
+ * storage order (populations[Q][N] of lbm_populations / lbm_init_populations;
+ * slot Q-1-i holds -c_i).  Host pointers. */
 lbm_status lbm_lattice_info(int32_t lattice, int32_t *Q, double *r, double *w, int32_t *c);
 
 /* ------------------------------------------------------------------------ */

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "liblbmx.so")
 
 LBM_ABI_VERSION = 1
 LBM_OK, LBM_EINVAL, LBM_EDEVICE, LBM_ENOMEM, LBM_EUNSUPPORTED, LBM_ELAUNCH = range(6)
-LBM_D1Q7, LBM_D2Q49, LBM_D3Q343 = 1, 2, 3
+LBM_D1Q7, LBM_D2Q49, LBM_D3Q343, LBM_D2Q37 = 1, 2, 3, 4
 LBM_F32, LBM_F64 = 0, 1
 LBM_BC_PERIODIC, LBM_BC_OPEN = 0, 1
 

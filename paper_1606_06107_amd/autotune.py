@@ -62,7 +62,7 @@ def tune_sim(sim, steps=20, reps=3, force=False):
     """Pick the fastest tile of the per-step kernel for this Sim (advances it
     by (len(tiles) * (reps + 1)) * steps steps).  Returns (tile, table)."""
     _load()
-    key = (f"step|D{sim.D}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|ip{sim._inplace}"
+    key = (f"step|D{sim.D}|lat{sim.lattice}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|ip{sim._inplace}"
            f"|blk{sim._blocked}|{_arch()}")
     if key in _mem and not force:
         t = tuple(_mem[key]["best"])

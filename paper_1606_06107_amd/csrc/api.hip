@@ -49,7 +49,10 @@ lbm_status check_device() {
     return LBM_OK;
 }
 
-int q_of(int lattice) { return lattice == LBM_D1Q7 ? 7 : lattice == LBM_D2Q49 ? 49 : 343; }
+int q_of(int lattice) {
+    return lattice == LBM_D1Q7 ? 7 : lattice == LBM_D2Q49 ? 49 : lattice == LBM_D2Q37 ? 37 : 343;
+}
+int kind_of(int lattice) { return lattice == LBM_D2Q37 ? lbmx::kD2Q37 : lbmx::kTensor; }
 size_t pop_bytes(int dtype) { return dtype == LBM_F32 ? 4 : 8; }
 
 void default_tile(int dim, int tile[3]) {
@@ -83,7 +86,7 @@ lbm_status validate(const lbm_desc *d) {
         return fail(LBM_EINVAL, "abi_version %d != %d", d->abi_version, LBM_ABI_VERSION);
     if (d->dim < 1 || d->dim > 3) return fail(LBM_EINVAL, "dim must be 1, 2 or 3");
     const int want = d->dim == 1 ? LBM_D1Q7 : d->dim == 2 ? LBM_D2Q49 : LBM_D3Q343;
-    if (d->lattice != want)
+    if (d->lattice != want && !(d->dim == 2 && d->lattice == LBM_D2Q37))
         return fail(LBM_EINVAL, "lattice %d does not match dim %d", d->lattice, d->dim);
     if (d->dtype != LBM_F32 && d->dtype != LBM_F64) return fail(LBM_EINVAL, "dtype must be F32 or F64");
     int64_t N = 1;
@@ -189,7 +192,7 @@ hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
     const bool mon = s->mon_every > 0 && s->t % s->mon_every == 0 &&
                      s->t / s->mon_every < s->mon_cap;
     a.partials = mon ? (double *)d.workspace : nullptr;
-    hipError_t e = lbmx::launch_step(d.dtype, d.dim, s->tile, a, st);
+    hipError_t e = lbmx::launch_step(d.dtype, d.dim, kind_of(d.lattice), s->tile, a, st);
     if (e != hipSuccess) return e;
     if (mon) {
         const int K = 2 + d.dim;
@@ -274,7 +277,7 @@ lbm_status lbm_init(const lbm_desc *desc, const double *rho, const double *u, co
     lbm_status st = make_sim(desc, hip_stream, &s);
     if (st) return st;
     lbmx::InitArgs a{rho, u, T, desc->f[0], desc->g[0], (uint32_t)N_of(*desc), s->blocked};
-    hipError_t e = lbmx::launch_init(desc->dtype, desc->dim, a, s->stream);
+    hipError_t e = lbmx::launch_init(desc->dtype, desc->dim, kind_of(desc->lattice), a, s->stream);
     if (e != hipSuccess) {
         lbm_destroy(s);
         return hip_fail(e, "init launch");
@@ -377,7 +380,7 @@ lbm_status lbm_moments(lbm_sim s, double *rho, double *u, double *T, double *tot
     a.partials = totals ? (double *)d.workspace : nullptr;
     if (!rho && !u && !T && !totals) return LBM_OK;
     int nb = 0;
-    hipError_t e = lbmx::launch_fields(d.dtype, d.dim, a, &nb, s->stream);
+    hipError_t e = lbmx::launch_fields(d.dtype, d.dim, kind_of(d.lattice), a, &nb, s->stream);
     if (e != hipSuccess) return hip_fail(e, "moments launch");
     if (totals) {
         e = lbmx::launch_reduce((const double *)d.workspace, nb, 2 + d.dim, totals, s->stream);
@@ -397,7 +400,7 @@ lbm_status lbm_populations(lbm_sim s, void *f_out, void *g_out) {
     lbmx::FieldArgs a = field_args(s);
     a.f_out = f_out;
     a.g_out = g_out;
-    hipError_t e = lbmx::launch_export(d.dtype, d.dim, a, s->stream);
+    hipError_t e = lbmx::launch_export(d.dtype, d.dim, kind_of(d.lattice), a, s->stream);
     if (e != hipSuccess) return hip_fail(e, "export launch");
     return LBM_OK;
 }
@@ -452,7 +455,7 @@ lbm_status lbm_set_blocked(lbm_sim s, int32_t enable) {
     } else {
         lbmx::FieldArgs a = field_args(s);
         a.f_out = d.f[dst];
-        e = lbmx::launch_export(d.dtype, d.dim, a, s->stream);
+        e = lbmx::launch_export(d.dtype, d.dim, kind_of(d.lattice), a, s->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "reorder launch");
     s->fcur = dst;
@@ -468,7 +471,7 @@ lbm_status lbm_set_blocked(lbm_sim s, int32_t enable) {
 lbm_status lbm_set_tile(lbm_sim s, int32_t tx, int32_t ty, int32_t tz) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     const int t[3] = {tx, ty, tz};
-    if (!lbmx::step_tile_supported(s->d.dtype, s->d.dim, t))
+    if (!lbmx::step_tile_supported(s->d.dtype, s->d.dim, kind_of(s->d.lattice), t))
         return fail(LBM_EUNSUPPORTED, "tile %dx%dx%d not compiled for dim %d", tx, ty, tz, s->d.dim);
     if (s->blocked && (tx != lbmx::kBlk || ty != 1 || tz != 1))
         return fail(LBM_EUNSUPPORTED, "the blocked population order runs with tile %dx1x1 only", lbmx::kBlk);
@@ -489,21 +492,26 @@ lbm_status lbm_destroy(lbm_sim s) {
 const char *lbm_last_error(void) { return g_err.c_str(); }
 
 lbm_status lbm_lattice_info(int32_t lattice, int32_t *Q, double *r, double *w, int32_t *c) {
-    if (lattice != LBM_D1Q7 && lattice != LBM_D2Q49 && lattice != LBM_D3Q343)
+    if (lattice != LBM_D1Q7 && lattice != LBM_D2Q49 && lattice != LBM_D3Q343 && lattice != LBM_D2Q37)
         return fail(LBM_EINVAL, "unknown lattice %d", lattice);
     const int q = q_of(lattice);
-    const int D = lattice == LBM_D1Q7 ? 1 : lattice == LBM_D2Q49 ? 2 : 3;
+    const int D = lattice == LBM_D1Q7 ? 1 : (lattice == LBM_D2Q49 || lattice == LBM_D2Q37) ? 2 : 3;
+    constexpr lbmx::DirTable<2, lbmx::kD2Q37> dirs37;
     if (Q) *Q = q;
     if (r) *r = lbmx::kR;
-    for (int i = 0; i < q; ++i) {
+    for (int s = 0; s < q; ++s) {
+        const int i = lattice == LBM_D2Q37 ? dirs37.v[s] : s;  // direction of storage slot s
         const int cx = lbmx::cx_of(i), cy = D >= 2 ? lbmx::cy_of(i) : 0, cz = D >= 3 ? lbmx::cz_of(i) : 0;
-        if (w)
-            w[i] = lbmx::kW1[cx < 0 ? -cx : cx] * (D >= 2 ? lbmx::kW1[cy < 0 ? -cy : cy] : 1.0) *
-                   (D >= 3 ? lbmx::kW1[cz < 0 ? -cz : cz] : 1.0);
+        if (w) {
+            if (lattice == LBM_D2Q37) w[s] = lbmx::Lat<2, lbmx::kD2Q37>::w(i);
+            else
+                w[s] = lbmx::kW1[cx < 0 ? -cx : cx] * (D >= 2 ? lbmx::kW1[cy < 0 ? -cy : cy] : 1.0) *
+                       (D >= 3 ? lbmx::kW1[cz < 0 ? -cz : cz] : 1.0);
+        }
         if (c) {
-            c[3 * i] = cx;
-            c[3 * i + 1] = cy;
-            c[3 * i + 2] = cz;
+            c[3 * s] = cx;
+            c[3 * s + 1] = cy;
+            c[3 * s + 2] = cz;
         }
     }
     return LBM_OK;

@@ -883,7 +883,7 @@ lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const d
     if (st) return st;
     if (!rho || !u || !T) return bfail(LBM_EINVAL, "rho, u, T must not be NULL");
     lbmx::InitArgs a{rho, u, T, desc->f[0], desc->g[0], (uint32_t)desc->total_nodes};
-    hipError_t e = lbmx::launch_init(desc->dtype, 1, a, (hipStream_t)hip_stream);
+    hipError_t e = lbmx::launch_init(desc->dtype, 1, lbmx::kTensor, a, (hipStream_t)hip_stream);
     if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("batch init: ") + hipGetErrorString(e));
     return LBM_OK;
 }
@@ -953,7 +953,7 @@ lbm_status lbm_batch_moments(const lbm_batch_desc *desc, double *rho, double *u,
     a.n_rot_inst = desc->n_rot;
     a.num_inst = (int)desc->num_instances;
     int nb = 0;
-    hipError_t e = lbmx::launch_fields(desc->dtype, 1, a, &nb, (hipStream_t)hip_stream);
+    hipError_t e = lbmx::launch_fields(desc->dtype, 1, lbmx::kTensor, a, &nb, (hipStream_t)hip_stream);
     if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("batch moments: ") + hipGetErrorString(e));
     return LBM_OK;
 }

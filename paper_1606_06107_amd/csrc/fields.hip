@@ -14,9 +14,9 @@ template <typename P> __device__ __forceinline__ P *pop_w(void *base, int i, uin
     return reinterpret_cast<P *>(base) + (size_t)i * N;
 }
 // Translational slot i of node x in either value order.
-template <typename P, int D>
+template <typename P, int D, int K>
 __device__ __forceinline__ P fget(const void *base, int blocked, uint32_t N, int i, uint32_t x) {
-    return reinterpret_cast<const P *>(base)[pop_index(blocked, Lat<D>::Q, N, i, x)];
+    return reinterpret_cast<const P *>(base)[pop_index(blocked, Lat<D, K>::Q, N, i, x)];
 }
 
 // Fixed-order workgroup reduction of K doubles; thread 0 writes dst[0..K-1].
@@ -44,15 +44,17 @@ __device__ __forceinline__ void block_totals(double (&v)[K], double *dst) {
 // Initial state: f = f^eq(rho,u,T), g = g^eq(T), evaluated in FP64, stored
 // streamed (kLayoutStreamed).
 // ---------------------------------------------------------------------------
-template <typename P, int D> __global__ void __launch_bounds__(256) k_init(InitArgs a) {
+template <typename P, int D, int K> __global__ void __launch_bounds__(256) k_init(InitArgs a) {
+    using L = Lat<D, K>;
     const uint32_t x = blockIdx.x * 256u + threadIdx.x;
     if (x >= a.N) return;
     const double uu[3] = {a.u[x], D >= 2 ? a.u[(size_t)a.N + x] : 0.0,
                           D >= 3 ? a.u[2 * (size_t)a.N + x] : 0.0};
     const FeqCoef<double> fc = feq_coef<double, D>(a.rho[x], uu, a.T[x]);
-    static_for<0, Lat<D>::Q>([&](auto I) {
+    static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        reinterpret_cast<P *>(a.f)[pop_index(a.blocked, Lat<D>::Q, a.N, i, x)] = (P)feq_dir<double, D, i>(fc);
+        reinterpret_cast<P *>(a.f)[pop_index(a.blocked, L::Q, a.N, i, x)] =
+            (P)feq_dir<double, D, L::dir(i), K>(fc);
     });
     const GeqCoef<double> gc = geq_coef<double>(a.T[x]);
     static_for<0, 7>([&](auto J) {
@@ -65,33 +67,36 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_init(InitA
 // Fields, totals and canonical export (runtime loop over populations).
 // ---------------------------------------------------------------------------
 // Node holding the value of f_i(x, t) for the buffer's layout (its slot is
-// src_slot).
-template <int D> __device__ __forceinline__ int src_slot(const FieldArgs &a, int i) {
-    return a.layout == kLayoutSwapped ? Lat<D>::Q - 1 - i : i;
+// src_slot); d = the direction of slot i.
+template <int D, int K> __device__ __forceinline__ int src_slot(const FieldArgs &a, int i) {
+    return a.layout == kLayoutSwapped ? Lat<D, K>::Q - 1 - i : i;
 }
 template <int D> __device__ __forceinline__ uint32_t src_index(const FieldArgs &a, int x, int y, int z,
-                                                              int i, int shift) {
-    const int sx = nb_coord(x, -cx_of(i) * shift, a.n0, a.open0);
-    const int sy = D >= 2 ? nb_coord(y, -cy_of(i) * shift, a.n1, a.open1) : 0;
-    const int sz = D >= 3 ? nb_coord(z, -cz_of(i) * shift, a.n2, a.open2) : 0;
+                                                              int d, int shift) {
+    const int sx = nb_coord(x, -cx_of(d) * shift, a.n0, a.open0);
+    const int sy = D >= 2 ? nb_coord(y, -cy_of(d) * shift, a.n1, a.open1) : 0;
+    const int sz = D >= 3 ? nb_coord(z, -cz_of(d) * shift, a.n2, a.open2) : 0;
     return (uint32_t)sx + (uint32_t)a.n0 * ((uint32_t)sy + (uint32_t)a.n1 * (uint32_t)sz);
 }
 
-template <typename P, int D> __global__ void __launch_bounds__(256) k_fields(FieldArgs a) {
+template <typename P, int D, int K> __global__ void __launch_bounds__(256) k_fields(FieldArgs a) {
+    using L = Lat<D, K>;
+    constexpr DirTable<D, K> dirs;
     const uint32_t x = blockIdx.x * 256u + threadIdx.x;
     const bool valid = x < a.N;
     const uint32_t xn = valid ? x : a.N - 1;
     const int cx = xn % a.n0, cy = (xn / a.n0) % a.n1, cz = xn / (a.n0 * a.n1);
     const int shift = a.layout == kLayoutStreamed ? 0 : 1;
     Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
-    for (int i = 0; i < Lat<D>::Q; ++i) {
-        const double v = (double)fget<P, D>(a.f, a.blocked, a.N, src_slot<D>(a, i),
-                                            src_index<D>(a, cx, cy, cz, i, shift));
+    for (int i = 0; i < L::Q; ++i) {
+        const int d = dirs.v[i];
+        const double v = (double)fget<P, D, K>(a.f, a.blocked, a.N, src_slot<D, K>(a, i),
+                                               src_index<D>(a, cx, cy, cz, d, shift));
         M.m0 += v;
-        M.m1[0] += cx_of(i) * v;
-        if (D >= 2) M.m1[1] += cy_of(i) * v;
-        if (D >= 3) M.m1[2] += cz_of(i) * v;
-        M.e2 += c2_of<D>(i) * v;
+        M.m1[0] += cx_of(d) * v;
+        if (D >= 2) M.m1[1] += cy_of(d) * v;
+        if (D >= 3) M.m1[2] += cz_of(d) * v;
+        M.e2 += c2_of<D>(d) * v;
     }
     for (int j = 0; j < 7; ++j) M.er += double((j - 3) * (j - 3)) * (double)pop<P>(a.g, j, a.N)[xn];
     double n_rot = a.n_rot;
@@ -121,15 +126,17 @@ template <typename P, int D> __global__ void __launch_bounds__(256) k_fields(Fie
     }
 }
 
-template <typename P, int D> __global__ void __launch_bounds__(256) k_export(FieldArgs a) {
+template <typename P, int D, int K> __global__ void __launch_bounds__(256) k_export(FieldArgs a) {
+    using L = Lat<D, K>;
+    constexpr DirTable<D, K> dirs;
     const uint32_t x = blockIdx.x * 256u + threadIdx.x;
     if (x >= a.N) return;
     const int cx = x % a.n0, cy = (x / a.n0) % a.n1, cz = x / (a.n0 * a.n1);
     const int shift = a.layout == kLayoutStreamed ? 0 : 1;
     if (a.f_out)
-        for (int i = 0; i < Lat<D>::Q; ++i)
-            pop_w<P>(a.f_out, i, a.N)[x] =
-                fget<P, D>(a.f, a.blocked, a.N, src_slot<D>(a, i), src_index<D>(a, cx, cy, cz, i, shift));
+        for (int i = 0; i < L::Q; ++i)
+            pop_w<P>(a.f_out, i, a.N)[x] = fget<P, D, K>(a.f, a.blocked, a.N, src_slot<D, K>(a, i),
+                                                         src_index<D>(a, cx, cy, cz, dirs.v[i], shift));
     if (a.g_out)
         for (int j = 0; j < 7; ++j) pop_w<P>(a.g_out, j, a.N)[x] = pop<P>(a.g, j, a.N)[x];
 }
@@ -180,17 +187,27 @@ hipError_t launch_to_blocked(int dtype, int Q, uint32_t N, const void *src, void
     return hipGetLastError();
 }
 
-hipError_t launch_init(int dtype, int dim, const InitArgs &a, hipStream_t s) {
+// Instantiate KERN<P, D, K> for the supported (dtype, dim, kind) and launch.
+#define LBMX_DISPATCH_PDK(KERN, g, b, s, a)                                            \
+    do {                                                                             \
+        if (kind == kD2Q37) {                                                        \
+            if (dim != 2) return hipErrorInvalidValue;                               \
+            if (dtype == 0) hipLaunchKernelGGL((KERN<float, 2, kD2Q37>), g, b, 0, s, a); \
+            else hipLaunchKernelGGL((KERN<double, 2, kD2Q37>), g, b, 0, s, a);       \
+        } else if (dtype == 0) {                                                     \
+            if (dim == 1) hipLaunchKernelGGL((KERN<float, 1, kTensor>), g, b, 0, s, a); \
+            else if (dim == 2) hipLaunchKernelGGL((KERN<float, 2, kTensor>), g, b, 0, s, a); \
+            else hipLaunchKernelGGL((KERN<float, 3, kTensor>), g, b, 0, s, a);        \
+        } else {                                                                     \
+            if (dim == 1) hipLaunchKernelGGL((KERN<double, 1, kTensor>), g, b, 0, s, a); \
+            else if (dim == 2) hipLaunchKernelGGL((KERN<double, 2, kTensor>), g, b, 0, s, a); \
+            else hipLaunchKernelGGL((KERN<double, 3, kTensor>), g, b, 0, s, a);       \
+        }                                                                            \
+    } while (0)
+
+hipError_t launch_init(int dtype, int dim, int kind, const InitArgs &a, hipStream_t s) {
     const dim3 g(blocks_for(a.N)), b(256);
-    if (dtype == 0) {
-        if (dim == 1) hipLaunchKernelGGL((k_init<float, 1>), g, b, 0, s, a);
-        else if (dim == 2) hipLaunchKernelGGL((k_init<float, 2>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_init<float, 3>), g, b, 0, s, a);
-    } else {
-        if (dim == 1) hipLaunchKernelGGL((k_init<double, 1>), g, b, 0, s, a);
-        else if (dim == 2) hipLaunchKernelGGL((k_init<double, 2>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_init<double, 3>), g, b, 0, s, a);
-    }
+    LBMX_DISPATCH_PDK(k_init, g, b, s, a);
     return hipGetLastError();
 }
 
@@ -201,12 +218,16 @@ int step_ntiles(int dim, const int tile[3], int n0, int n1, int n2, int *t0, int
     return *t0 * *t1 * *t2;
 }
 
-bool step_tile_supported(int dtype, int dim, const int tile[3]) {
+bool step_tile_supported(int dtype, int dim, int kind, const int tile[3]) {
     (void)dtype;
     bool ok = false;
 #define C1(TXv, TYv) ok = ok || (dim == 1 && tile[0] == TXv && tile[1] == 1 && tile[2] == 1);
 #define C2(TXv, TYv) ok = ok || (dim == 2 && tile[0] == TXv && tile[1] == TYv && tile[2] == 1);
 #define C3(TXv, TYv) ok = ok || (dim == 3 && tile[0] == TXv && tile[1] == TYv && tile[2] == 1);
+    if (kind == kD2Q37) {
+        LBMX_TILES_37(C2)
+        return ok;
+    }
     LBMX_TILES_1D(C1)
     LBMX_TILES_2D(C2)
     LBMX_TILES_3D(C3)
@@ -216,37 +237,22 @@ bool step_tile_supported(int dtype, int dim, const int tile[3]) {
     return ok;
 }
 
-hipError_t launch_step(int dtype, int dim, const int tile[3], const StepArgs &a, hipStream_t s) {
+hipError_t launch_step(int dtype, int dim, int kind, const int tile[3], const StepArgs &a, hipStream_t s) {
+    if (kind == kD2Q37) return dtype == 0 ? launch_step_37_f32(tile, a, s) : launch_step_37_f64(tile, a, s);
     if (dim == 3) return launch_step_3(dtype, tile, a, s);
     return dtype == 0 ? launch_step_12_f32(dim, tile, a, s) : launch_step_12_f64(dim, tile, a, s);
 }
 
-hipError_t launch_fields(int dtype, int dim, const FieldArgs &a, int *nblocks, hipStream_t s) {
+hipError_t launch_fields(int dtype, int dim, int kind, const FieldArgs &a, int *nblocks, hipStream_t s) {
     const dim3 g(blocks_for(a.N)), b(256);
     *nblocks = (int)g.x;
-    if (dtype == 0) {
-        if (dim == 1) hipLaunchKernelGGL((k_fields<float, 1>), g, b, 0, s, a);
-        else if (dim == 2) hipLaunchKernelGGL((k_fields<float, 2>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_fields<float, 3>), g, b, 0, s, a);
-    } else {
-        if (dim == 1) hipLaunchKernelGGL((k_fields<double, 1>), g, b, 0, s, a);
-        else if (dim == 2) hipLaunchKernelGGL((k_fields<double, 2>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_fields<double, 3>), g, b, 0, s, a);
-    }
+    LBMX_DISPATCH_PDK(k_fields, g, b, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_export(int dtype, int dim, const FieldArgs &a, hipStream_t s) {
+hipError_t launch_export(int dtype, int dim, int kind, const FieldArgs &a, hipStream_t s) {
     const dim3 g(blocks_for(a.N)), b(256);
-    if (dtype == 0) {
-        if (dim == 1) hipLaunchKernelGGL((k_export<float, 1>), g, b, 0, s, a);
-        else if (dim == 2) hipLaunchKernelGGL((k_export<float, 2>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_export<float, 3>), g, b, 0, s, a);
-    } else {
-        if (dim == 1) hipLaunchKernelGGL((k_export<double, 1>), g, b, 0, s, a);
-        else if (dim == 2) hipLaunchKernelGGL((k_export<double, 2>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_export<double, 3>), g, b, 0, s, a);
-    }
+    LBMX_DISPATCH_PDK(k_export, g, b, s, a);
     return hipGetLastError();
 }
 

@@ -77,27 +77,31 @@ struct InitArgs {
 // Copy plain populations src[Q][N] into dst in blocked order.
 hipError_t launch_to_blocked(int dtype, int Q, uint32_t N, const void *src, void *dst, hipStream_t s);
 
-hipError_t launch_init(int dtype, int dim, const InitArgs &a, hipStream_t s);
+// kind: lattice kind (kTensor, or kD2Q37 with dim 2; lbm_device.hpp).
+hipError_t launch_init(int dtype, int dim, int kind, const InitArgs &a, hipStream_t s);
 // Message returned by lbm_last_error() on this thread.
 void set_error(const char *msg);
 // tile = {tx, ty, tz}; returns hipErrorInvalidValue for a shape not compiled.
-hipError_t launch_step(int dtype, int dim, const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step(int dtype, int dim, int kind, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_12_f32(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_12_f64(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_12_f32_inplace(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_12_f64_inplace(int dim, const int tile[3], const StepArgs &a, hipStream_t s);
 hipError_t launch_step_3(int dtype, const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step_37_f32(const int tile[3], const StepArgs &a, hipStream_t s);
+hipError_t launch_step_37_f64(const int tile[3], const StepArgs &a, hipStream_t s);
 
 // Compiled tile shapes (nodes per workgroup along x, y).
 #define LBMX_TILES_1D(X) X(64, 1) X(128, 1) X(256, 1) X(512, 1) X(1024, 1)
 #define LBMX_TILES_2D(X) X(64, 4) X(32, 8) X(128, 2) X(256, 1) X(64, 8) X(32, 16) X(16, 16) X(64, 2)
 #define LBMX_TILES_3D(X) X(64, 1) X(32, 2) X(16, 4)
-bool step_tile_supported(int dtype, int dim, const int tile[3]);
+#define LBMX_TILES_37(X) X(256, 1) X(128, 2) X(64, 2) X(64, 4) X(32, 8)
+bool step_tile_supported(int dtype, int dim, int kind, const int tile[3]);
 // Tiles (and therefore partial rows) of a step launch with this tile shape.
 int step_ntiles(int dim, const int tile[3], int n0, int n1, int n2, int *t0, int *t1, int *t2);
 // Fields and/or per-block partial totals; returns the number of blocks used.
-hipError_t launch_fields(int dtype, int dim, const FieldArgs &a, int *nblocks, hipStream_t s);
-hipError_t launch_export(int dtype, int dim, const FieldArgs &a, hipStream_t s);
+hipError_t launch_fields(int dtype, int dim, int kind, const FieldArgs &a, int *nblocks, hipStream_t s);
+hipError_t launch_export(int dtype, int dim, int kind, const FieldArgs &a, hipStream_t s);
 // Fixed-order sum of partials[nparts][K] into out[K] (one workgroup).
 hipError_t launch_reduce(const double *partials, int nparts, int K, double *out, hipStream_t s);
 

@@ -18,9 +18,6 @@ namespace lbmx {
 constexpr double kR = LBM_R;
 constexpr double kW1[4] = {LBM_W1_0, LBM_W1_1, LBM_W1_2, LBM_W1_3};
 
-template <int D> struct Lat {
-    static constexpr int Q = D == 1 ? 7 : (D == 2 ? 49 : 343);
-};
 __host__ __device__ constexpr int cx_of(int i) { return i % 7 - 3; }
 __host__ __device__ constexpr int cy_of(int i) { return (i / 7) % 7 - 3; }
 __host__ __device__ constexpr int cz_of(int i) { return (i / 49) % 7 - 3; }
@@ -33,6 +30,49 @@ template <int D> __host__ __device__ constexpr double w_of(int i) {
     return kW1[iabs(cx_of(i))] * (D >= 2 ? kW1[iabs(cy_of(i))] : 1.0) *
            (D >= 3 ? kW1[iabs(cz_of(i))] : 1.0);
 }
+
+// D2Q37 (Table I): the D2Q49 velocities without the groups (2,2) and (3,2),
+// one weight per group (p, q) = (max, min of |c_x|, |c_y|), at the same r.
+constexpr double kW37[8] = {LBM_W37_0, LBM_W37_1, LBM_W37_2, LBM_W37_3,
+                            LBM_W37_4, LBM_W37_5, LBM_W37_6, LBM_W37_7};
+__host__ __device__ constexpr int d37_group(int i) {  // -1: not a D2Q37 velocity
+    const int ax = iabs(cx_of(i)), ay = iabs(cy_of(i));
+    const int p = ax > ay ? ax : ay, q = ax > ay ? ay : ax;
+    if (p == 0) return 0;
+    if (p == 1) return q == 0 ? 1 : 2;
+    if (p == 2) return q == 0 ? 3 : (q == 1 ? 4 : -1);
+    return q == 0 ? 5 : (q == 1 ? 6 : (q == 3 ? 7 : -1));
+}
+
+// Lattice kinds.  A population's storage slot s runs over 0..Q-1; its
+// velocity is direction dir(s) of the base-7 enumeration above (the
+// identity for the tensor lattices), so that slot Q-1-s holds -c.
+enum { kTensor = 0, kD2Q37 = 1 };
+template <int D, int K = kTensor> struct Lat {
+    static constexpr int Q = D == 1 ? 7 : (D == 2 ? 49 : 343);
+    __host__ __device__ static constexpr int dir(int s) { return s; }
+    __host__ __device__ static constexpr double w(int d) { return w_of<D>(d); }
+};
+template <> struct Lat<2, kD2Q37> {
+    static constexpr int Q = 37;
+    __host__ __device__ static constexpr int dir(int s) {
+        int k = 0;
+        for (int i = 0; i < 49; ++i)
+            if (d37_group(i) >= 0) {
+                if (k == s) return i;
+                ++k;
+            }
+        return -1;
+    }
+    __host__ __device__ static constexpr double w(int d) { return kW37[d37_group(d)]; }
+};
+// Slot -> direction as a table, for loops with a run-time slot index.
+template <int D, int K> struct DirTable {
+    int v[Lat<D, K>::Q];
+    constexpr DirTable() : v() {
+        for (int s = 0; s < Lat<D, K>::Q; ++s) v[s] = Lat<D, K>::dir(s);
+    }
+};
 
 // Compile-time loop: calls f(std::integral_constant-like) for I = B..E-1.
 template <int I> struct Int { static constexpr int value = I; };
@@ -121,7 +161,7 @@ template <typename P, int D> __device__ __forceinline__ FeqCoef<P> feq_coef(P rh
     return c;
 }
 
-template <typename P, int D, int I> __device__ __forceinline__ P feq_dir(const FeqCoef<P> &c) {
+template <typename P, int D, int I, int K = kTensor> __device__ __forceinline__ P feq_dir(const FeqCoef<P> &c) {
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     constexpr double xi2d = kR * kR * c2_of<D>(I);
     const P xi2 = P(xi2d);
@@ -132,7 +172,7 @@ template <typename P, int D, int I> __device__ __forceinline__ P feq_dir(const F
     const P p1 = c.B0 + xi2 * c.B1;
     const P p2 = c.C0 + xi2 * c.C1;
     const P poly = p0 + a * (p1 + a * (p2 + a * (P(1.0 / 6.0) + a * P(1.0 / 24.0))));
-    return P(w_of<D>(I)) * c.rho * poly;
+    return P(Lat<D, K>::w(I)) * c.rho * poly;
 }
 
 // ---------------------------------------------------------------------------
@@ -241,7 +281,7 @@ __device__ __forceinline__ void stp_stream(void *base, int i, uint32_t N, uint32
 // Equilibrium of the direction pair (c, -c): with a = c.ru,
 //   f^eq(+-c) / (w rho) = E(a^2) +- a O(a^2),  E = P0 + a^2 (P2 + a^2/24),
 //   O = P1 + a^2/6   (same polynomial as feq_dir).
-template <typename P, int D, int I>
+template <typename P, int D, int I, int K = kTensor>
 __device__ __forceinline__ void feq_pair(const FeqCoef<P> &c, P &fplus, P &fminus) {
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     constexpr double xi2d = kR * kR * c2_of<D>(I);
@@ -255,7 +295,7 @@ __device__ __forceinline__ void feq_pair(const FeqCoef<P> &c, P &fplus, P &fminu
     const P p2 = c.C0 + xi2 * c.C1;
     const P E = p0 + a2 * (p2 + a2 * P(1.0 / 24.0));
     const P O = (p1 + a2 * P(1.0 / 6.0)) * a;
-    const P wr = P(w_of<D>(I)) * c.rho;
+    const P wr = P(Lat<D, K>::w(I)) * c.rho;
     const P wE = wr * E;
     fplus = wE + wr * O;
     fminus = wE - wr * O;

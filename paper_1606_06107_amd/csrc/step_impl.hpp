@@ -158,11 +158,14 @@ __device__ __forceinline__ void rot_relax_store(const P (&gv)[7], const P (&adv)
 template <typename P, int D> constexpr int kWavesMin = sizeof(P) == 4 ? (D == 2 ? 3 : 4) : 2;
 template <typename P, int D> constexpr int kWavesMax = (sizeof(P) == 4 && D == 2) ? 3 : 8;
 
-template <typename P, int D, int TX, int TY, int S>
+template <typename P, int D, int TX, int TY, int S, int K = kTensor>
 __global__ void __launch_bounds__(TX *TY)
 __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12(StepArgs a) {
     static_assert(!(sizeof(P) == 4 && D == 2) || TX * TY <= 512, "3 waves per SIMD needs <= 512 threads");
-    constexpr int Q = Lat<D>::Q;
+    // Populations by storage slot i (0..Q-1), velocity c of direction
+    // L::dir(i); slot Q-1-i holds -c, slot H the rest population.
+    using L = Lat<D, K>;
+    constexpr int Q = L::Q;
     constexpr int H = Q / 2;  // rest direction c = 0; pairs (i, Q-1-i) for i < H
     constexpr int NT = TX * TY;
     constexpr int NS = 2 * D + 1;  // populations absorbing the FP32 defects
@@ -213,15 +216,15 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     uint32_t sox[7], soy[7];  // scatter offsets of x + c (odd in-place step, edge waves)
     if constexpr (S == kSchemeInPlaceEven) {
         static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
+            constexpr int i = decltype(I)::value, d = L::dir(i);
             fv[i] = ld_buf<P, 0>(pop_rsrc(a.f_in, i, N, SZ), nodeb, 0u);
         });
     } else {
         if (fast) {
             static_for<0, Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
+                constexpr int i = decltype(I)::value, d = L::dir(i);
                 const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.f_in, slot_in(i), N, SZ);
-                fv[i] = ld_buf<P, CPL>(r, vb + (3 - cx_of(i)) * SZ, D >= 2 ? rowo[3 - cy_of(i)] : 0u);
+                fv[i] = ld_buf<P, CPL>(r, vb + (3 - cx_of(d)) * SZ, D >= 2 ? rowo[3 - cy_of(d)] : 0u);
             });
         } else {
             const int shift = (PP && a.layout == kLayoutStreamed) ? 0 : 1;
@@ -236,8 +239,8 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
                 }
             }
             static_for<0, Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                const uint32_t off = ox[cx_of(i) + 3] + (D >= 2 ? oy[cy_of(i) + 3] : 0u);
+                constexpr int i = decltype(I)::value, d = L::dir(i);
+                const uint32_t off = ox[cx_of(d) + 3] + (D >= 2 ? oy[cy_of(d) + 3] : 0u);
                 if constexpr (PP) fv[i] = ld_nt<P>(fin + i * PS, off);
                 else fv[i] = ld<P>(fin + slot_in(i) * PS, off);
             });
@@ -247,7 +250,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     // even in-place slot opp(i) at x; odd in-place slot i at x + c_i.
     const uint32_t nodeb_st = valid ? nodeb : kDropOffset;
     auto store_f = [&](auto I, P v) {
-        constexpr int i = decltype(I)::value;
+        constexpr int i = decltype(I)::value, d = L::dir(i);
         if constexpr (PP) {
             st<P>(a.f_out, i, N, nodeb, v);
         } else if constexpr (S == kSchemeInPlaceEven) {
@@ -255,9 +258,9 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
         } else {
             const __amdgpu_buffer_rsrc_t r = pop_rsrc(a.f_out, i, N, SZ);
             if (fast)
-                st_buf<P, 0>(r, vb + (3 + cx_of(i)) * SZ, D >= 2 ? rowo[3 + cy_of(i)] : 0u, v);
+                st_buf<P, 0>(r, vb + (3 + cx_of(d)) * SZ, D >= 2 ? rowo[3 + cy_of(d)] : 0u, v);
             else
-                st_buf<P, 0>(r, valid ? sox[cx_of(i) + 3] + (D >= 2 ? soy[cy_of(i) + 3] : 0u) : kDropOffset,
+                st_buf<P, 0>(r, valid ? sox[cx_of(d) + 3] + (D >= 2 ? soy[cy_of(d) + 3] : 0u) : kDropOffset,
                              0u, v);
         }
     };
@@ -268,10 +271,10 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     // 2. FP64 moments via per-column (cx) and per-row (cy) sums.
     double col[7] = {0, 0, 0, 0, 0, 0, 0}, row[7] = {0, 0, 0, 0, 0, 0, 0};
     static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+        constexpr int i = decltype(I)::value, d = L::dir(i);
         const double v = (double)fv[i];
-        col[cx_of(i) + 3] += v;
-        if constexpr (D >= 2) row[cy_of(i) + 3] += v;
+        col[cx_of(d) + 3] += v;
+        if constexpr (D >= 2) row[cy_of(d) + 3] += v;
     });
     Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
 #pragma unroll
@@ -308,24 +311,24 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     P cs[7] = {0, 0, 0, 0, 0, 0, 0}, rs[7] = {0, 0, 0, 0, 0, 0, 0};  // FP32 sums
     // Increment d = omega (f^eq - f), each use written as one multiply-add.
     auto relax = [&](auto I, P fe) {
-        constexpr int i = decltype(I)::value;
-        constexpr int sr = special_rank<D>(i);
+        constexpr int i = decltype(I)::value, d = L::dir(i);
+        constexpr int sr = special_rank<D>(d);
         const P df = fe - fv[i];
         if constexpr (F32) {
-            cs[cx_of(i) + 3] += om * df;
-            if constexpr (D >= 2) rs[cy_of(i) + 3] += om * df;
+            cs[cx_of(d) + 3] += om * df;
+            if constexpr (D >= 2) rs[cy_of(d) + 3] += om * df;
         }
         if constexpr (F32 && sr >= 0) dsp[sr] = om * df;
         else store_f(Int<i>{}, fv[i] + om * df);
     };
     static_for<0, H>([&](auto I) {
-        constexpr int i = decltype(I)::value, k = Q - 1 - i;
+        constexpr int i = decltype(I)::value, k = Q - 1 - i, d = L::dir(i);
         P fp, fm;
-        feq_pair<P, D, i>(fc, fp, fm);
+        feq_pair<P, D, d, K>(fc, fp, fm);
         relax(Int<i>{}, fp);
         relax(Int<k>{}, fm);
     });
-    relax(Int<H>{}, P(w_of<D>(H)) * fc.rho * fc.A0);
+    relax(Int<H>{}, P(L::w(L::dir(H))) * fc.rho * fc.A0);
     if constexpr (F32) {
         double S0 = 0.0, S1[3] = {0.0, 0.0, 0.0}, S2 = 0.0;
 #pragma unroll
@@ -345,8 +348,8 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
         const double R1[3] = {-S1[0], -S1[1], 0.0};
         const Eps ep = eps_from_defects<D>(-S0, R1, t2 - S2);
         static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int sr = special_rank<D>(i);
+            constexpr int i = decltype(I)::value, d = L::dir(i);
+            constexpr int sr = special_rank<D>(d);
             if constexpr (sr >= 0) store_f(Int<i>{}, fv[i] + (dsp[sr] + (P)ep.e[sr]));
         });
     }
@@ -685,6 +688,21 @@ bool launch_12(int dim, const int tile[3], const StepArgs &a, hipStream_t s) {
     LBMX_TILES_2D(L2)
 #undef L1
 #undef L2
+    return done;
+}
+
+// Launch k_step_12<P, 2, tile, S, kD2Q37> for a compiled D2Q37 tile shape.
+template <typename P, int S>
+bool launch_37(const int tile[3], const StepArgs &a, hipStream_t s) {
+    const dim3 grid(a.ntiles);
+    bool done = false;
+#define L37(TXv, TYv)                                                                                 \
+    if (!done && tile[0] == TXv && tile[1] == TYv) {                                                  \
+        hipLaunchKernelGGL((k_step_12<P, 2, TXv, TYv, S, kD2Q37>), grid, dim3(TXv * TYv), 0, s, a); \
+        done = true;                                                                                  \
+    }
+    LBMX_TILES_37(L37)
+#undef L37
     return done;
 }
 

@@ -11,22 +11,28 @@ from . import _lib as L
 
 _LATTICE = {1: L.LBM_D1Q7, 2: L.LBM_D2Q49, 3: L.LBM_D3Q343}
 _Q = {1: 7, 2: 49, 3: 343}
+_NAMED = {"D1Q7": (1, L.LBM_D1Q7, 7), "D2Q49": (2, L.LBM_D2Q49, 49), "D2Q37": (2, L.LBM_D2Q37, 37),
+          "D3Q343": (3, L.LBM_D3Q343, 343)}
 
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def lattice_info(dim: int):
-    """(Q, r, w[Q], c[Q,3]) as the library computes with them."""
+def lattice_info(dim_or_name):
+    """(Q, r, w[Q], c[Q,3]) as the library computes with them, by dimension
+    (tensor lattices) or name ("D2Q37", ...); rows in storage-slot order."""
     import numpy as np
     lib = L.load()
     Q = ctypes.c_int32()
     r = ctypes.c_double()
-    q = _Q[dim]
+    if isinstance(dim_or_name, str):
+        _, lat, q = _NAMED[dim_or_name]
+    else:
+        lat, q = _LATTICE[dim_or_name], _Q[dim_or_name]
     w = np.zeros(q)
     c = np.zeros((q, 3), dtype=np.int32)
-    L.check(lib.lbm_lattice_info(_LATTICE[dim], ctypes.byref(Q), ctypes.byref(r),
+    L.check(lib.lbm_lattice_info(lat, ctypes.byref(Q), ctypes.byref(r),
                                  w.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p)))
     return Q.value, r.value, w, c
 
@@ -38,10 +44,11 @@ class Sim:
 
     shape: nodes per axis (x first), bc: 'periodic' | 'open' per axis,
     n_rot: rotational degrees of freedom (gamma = (D+n+2)/(D+n)), tau: BGK
-    relaxation time in steps, dtype: torch.float32 | torch.float64."""
+    relaxation time in steps, dtype: torch.float32 | torch.float64, lattice:
+    None (D1Q7^D) or "D2Q37" (2-D, Table I)."""
 
     def __init__(self, shape, bc=None, n_rot=0.0, tau=1.0, dtype=torch.float32,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, lattice=None):
         self.lib = L.load()
         shape = tuple(int(s) for s in shape)
         self.D = len(shape)
@@ -50,7 +57,11 @@ class Sim:
         self.N = 1
         for s in shape:
             self.N *= s
-        self.Q = _Q[self.D]
+        if lattice is None:
+            self.lattice, self.Q = _LATTICE[self.D], _Q[self.D]
+        else:
+            dim, self.lattice, self.Q = _NAMED[lattice]
+            assert dim == self.D, f"{lattice} needs a {dim}-D grid"
         bc = bc or ["periodic"] * self.D
         self.dtype = dtype
         self.device = torch.device(device)
@@ -64,7 +75,7 @@ class Sim:
         for a in range(3):
             d.n[a] = n[a]
             d.bc[a] = L.LBM_BC_OPEN if (a < self.D and bc[a] == "open") else L.LBM_BC_PERIODIC
-        d.lattice = _LATTICE[self.D]
+        d.lattice = self.lattice
         d.dtype = L.LBM_F32 if dtype == torch.float32 else L.LBM_F64
         d.n_rot = float(n_rot)
         d.tau = float(tau)

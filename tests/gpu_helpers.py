@@ -8,6 +8,7 @@ import oracle
 import workloads
 
 _OKIND = {1: oracle.D1Q7, 2: oracle.D2Q49, 3: oracle.D3Q343}
+_ONAMED = {"D2Q37": oracle.D2Q37}
 
 
 def announce(msg):
@@ -16,10 +17,11 @@ def announce(msg):
 
 
 def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile=None,
-            graphs=True, chunks=None, inplace=None, blocked=None):
+            graphs=True, chunks=None, inplace=None, blocked=None, lattice=None):
+    """Populations come back in the library's slot order (lattice_info)."""
     import torch
     from paper_1606_06107_amd import Sim
-    sim = Sim(shape, bc=bc, n_rot=n_rot, tau=tau, dtype=dtype).init(*fields)
+    sim = Sim(shape, bc=bc, n_rot=n_rot, tau=tau, dtype=dtype, lattice=lattice).init(*fields)
     if perturb_seed is not None:
         f, g = sim.populations()
         pf = torch.as_tensor(workloads.nonequilibrium_perturbation(f.shape, perturb_seed)).to(f)
@@ -41,10 +43,11 @@ def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile
             "tot": tot.cpu().numpy(), "f": f.double().cpu().numpy(), "g": g.double().cpu().numpy()}
 
 
-def oracle_run(shape, bc, n_rot, tau, fields, steps, perturb_seed=None):
+def oracle_run(shape, bc, n_rot, tau, fields, steps, perturb_seed=None, lattice=None):
+    """Populations come back in the oracle's order (oracle.lattice)."""
     D = len(shape)
     obc = [oracle.OPEN if b == "open" else oracle.PERIODIC for b in bc]
-    G = oracle.Grid(_OKIND[D], shape, bc=obc, n_rot=n_rot, tau=tau)
+    G = oracle.Grid(_ONAMED[lattice] if lattice else _OKIND[D], shape, bc=obc, n_rot=n_rot, tau=tau)
     f, g = G.init_eq(*fields)
     if perturb_seed is not None:
         f *= workloads.nonequilibrium_perturbation(f.shape, perturb_seed)
@@ -94,3 +97,9 @@ def smooth_fields(shape, seed, mach=0.3, gamma=1.4):
     u = np.stack([0.15 * modes(rng) for _ in range(D)])
     T = 1 + 0.05 * modes(rng)
     return rho, u, T
+
+
+def slot_permutation(c_lib, c_orc):
+    """perm with c_orc[perm[s]] == c_lib[s]: oracle rows in library slot order."""
+    index = {tuple(int(v) for v in row[:2]): k for k, row in enumerate(np.asarray(c_orc))}
+    return np.array([index[tuple(int(v) for v in row[:2])] for row in np.asarray(c_lib)])

@@ -134,7 +134,7 @@ def test_batch_validation(lib):
     assert L.lbm_batch_step(ctypes.byref(bd), None) == lib.LBM_EINVAL
 
 
-@pytest.mark.parametrize("dim,kind", [(1, "D1Q7"), (2, "D2Q49"), (3, "D3Q343")])
+@pytest.mark.parametrize("dim,kind", [(1, "D1Q7"), (2, "D2Q49"), (3, "D3Q343"), ("D2Q37", "D2Q37")])
 def test_library_lattice_agrees_with_oracle(lib, orc, dim, kind):
     from paper_1606_06107_amd import lattice_info
     Q, r, w, c = lattice_info(dim)
@@ -143,6 +143,12 @@ def test_library_lattice_agrees_with_oracle(lib, orc, dim, kind):
     # 50-digit derivation (library) vs FP64 bisection on the moment residual
     # (oracle): agreement to the oracle's root-finding accuracy
     assert r == pytest.approx(ro, rel=1e-14)
+    if kind == "D2Q37":  # same velocity set, the library's slot order (slot Q-1-s holds -c_s)
+        index = {tuple(int(v) for v in row[:2]): k for k, row in enumerate(co)}
+        perm = np.array([index[tuple(int(v) for v in row[:2])] for row in c])
+        assert sorted(perm) == list(range(Q))
+        assert np.array_equal(c[::-1], -c)
+        co, wo = co[perm], wo[perm]
     assert np.array_equal(c, co)
     assert np.allclose(w, wo, rtol=1e-13, atol=0)
 
