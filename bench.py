@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # (profiles/k_step_12_d2q49_1024x1024_fp32.md), per tile shape; valid only for
 # the sources they were taken on (sha256 of the files below).
 TRAFFIC = {"nodes": 1024 * 1024, "inplace": True,
-           "bytes": {(256, 1): 490_136_269, (128, 2): 488_639_130, (64, 2): 492_638_259},
-           "sha256": "8c77feacbd58dda05df820561ad26ec243c9beda53fbd47e182af9c35907dacd"}
+           "bytes": {(256, 1): 489_276_211, (128, 2): 489_725_901, (64, 2): 491_665_357, (64, 4): 491_099_341},
+           "sha256": "c553cce5833f16c56f9dcdd3d9ea0471cccee0daf7fc397ca083963326de0d0c"}
 TRAFFIC_SOURCES = ('paper_1606_06107_amd/csrc/step_impl.hpp', 'paper_1606_06107_amd/csrc/lbm_device.hpp', 'paper_1606_06107_amd/csrc/launch.hpp', 'paper_1606_06107_amd/csrc/step_12_f32_inplace.hip', 'paper_1606_06107_amd/_build.py')
 
 
