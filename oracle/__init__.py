@@ -48,7 +48,8 @@ def build(force: bool = True) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("lattice", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("bc", ctypes.c_int32 * 3),
-                ("n_rot", ctypes.c_double), ("tau", ctypes.c_double)]
+                ("n_rot", ctypes.c_double), ("tau", ctypes.c_double),
+                ("fd_courant", ctypes.c_double)]
 
 
 _lib = None
@@ -125,10 +126,13 @@ def geq(theta: float) -> np.ndarray:
 
 
 class Grid:
-    """A grid of nodes with one lattice, boundary conditions, n and tau."""
+    """A grid of nodes with one lattice, boundary conditions, n and tau.
+    fd_courant = 0: the collide-and-stream update; lambda > 0: the
+    finite-difference update of Sec. V A for f as well, with time step
+    lambda times the streaming step (tau stays in streaming steps)."""
 
     def __init__(self, lattice_kind: int, shape, bc=(PERIODIC, PERIODIC, PERIODIC),
-                 n_rot: float = 0.0, tau: float = 1.0):
+                 n_rot: float = 0.0, tau: float = 1.0, fd_courant: float = 0.0):
         D = _DIMOF[lattice_kind]
         shape = tuple(int(s) for s in shape)
         assert len(shape) == D, "shape must have one entry per spatial dimension"
@@ -137,8 +141,9 @@ class Grid:
         self.kind, self.D, self.Q = lattice_kind, D, _QOF[lattice_kind]
         self.shape, self.N = shape, int(np.prod(shape))
         self.n_rot, self.tau = float(n_rot), float(tau)
+        self.fd_courant = float(fd_courant)
         self._g = _Grid(D, lattice_kind, (ctypes.c_int64 * 3)(*n), (ctypes.c_int32 * 3)(*bcs),
-                        self.n_rot, self.tau)
+                        self.n_rot, self.tau, self.fd_courant)
 
     def init_eq(self, rho, u, T):
         """f = f^eq(rho, u, T), g = g^eq(T) at every node.  u is [D][N]."""

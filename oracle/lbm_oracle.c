@@ -292,7 +292,11 @@ typedef struct {
     int64_t n[3];       /* nodes per axis, unused axes = 1 */
     int32_t bc[3];      /* 0 = periodic, 1 = open (zero-gradient clamp) */
     double n_rot;       /* rotational degrees of freedom n */
-    double tau;         /* relaxation time in time steps */
+    double tau;         /* relaxation time in time steps of the streaming update */
+    double fd_courant;  /* 0: collide-and-stream update of the translational
+                           populations (reading A); lambda > 0: the finite-difference
+                           update written in Sec. V A (reading B) with time step
+                           lambda / r, i.e. lambda times the streaming step */
 } orc_grid;
 
 typedef struct {
@@ -446,11 +450,68 @@ static void one_step(const orc_grid *G, const lat_t *L, double *f, double *g, do
     }
 }
 
+/* One time step of the finite-difference form of Sec. V A for both kinds of
+ * population (reading B of the translational update): with time step
+ * dt = lambda / r (lambda = G->fd_courant) and dx = 1,
+ *   f_i(x, t+dt) = f_i - sum_a (lambda c_ia) D_a[f_i] - (lambda/tau) (f_i - f_i^eq)
+ *   g_j(x, t+dt) = g_j - sum_a (lambda u_a / r) D_a[g_j] - (lambda/tau) (g_j - g_j^eq)
+ * where D_a is the third-order upwind difference along axis a oriented by the
+ * sign of the Courant number (xi_ia dt / dx = lambda c_ia for f, u_a dt / dx
+ * for g), every term evaluated at time t (forward Euler), and tau the
+ * relaxation time in streaming steps (1/r), so the collision term is dt/tau
+ * in time units.  lambda = 1 is the time step of the streaming update. */
+static void one_step_fd(const orc_grid *G, const lat_t *L, double *f, double *g, double *fs,
+                        double *gs)
+{
+    int64_t N = nnodes(G);
+    const double lam = G->fd_courant;
+    const double omega = lam / G->tau;
+    int64_t N0 = G->n[0], N1 = G->n[1];
+
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        double fn[ORC_MAXQ], gn[7], fe[ORC_MAXQ], ge[7], u[3], rho, T;
+        for (int i = 0; i < L->Q; ++i) fn[i] = f[i * N + x];
+        for (int j = 0; j < 7; ++j) gn[j] = g[j * N + x];
+        node_moments(L, G->n_rot, fn, gn, &rho, u, &T, NULL);
+        orc_feq(L->D, L->Q, L->c, L->w, L->r, rho, u, T, fe);
+        geq_on(L->eta, L->wr, T, ge);
+        int64_t xyz[3] = {x % N0, (x / N0) % N1, x / (N0 * N1)};
+        for (int i = 0; i < L->Q; ++i) {
+            double adv = 0.0;
+            for (int a = 0; a < L->D; ++a) {
+                double nu = lam * L->c[i * 3 + a];
+                if (nu != 0.0) adv += nu * upwind3(G, f + i * N, xyz, a, nu);
+            }
+            fs[i * N + x] = fn[i] - adv - omega * (fn[i] - fe[i]);
+        }
+        for (int j = 0; j < 7; ++j) {
+            double adv = 0.0;
+            for (int a = 0; a < L->D; ++a) {
+                double nu = lam * u[a] / L->r;
+                adv += nu * upwind3(G, g + j * N, xyz, a, nu);
+            }
+            gs[j * N + x] = gn[j] - adv - omega * (gn[j] - ge[j]);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; ++x) {
+        for (int i = 0; i < L->Q; ++i) f[i * N + x] = fs[i * N + x];
+        for (int j = 0; j < 7; ++j) g[j * N + x] = gs[j * N + x];
+    }
+}
+
 /* Advance nsteps time steps in place.  fs/gs: caller scratch, same sizes as f/g. */
 int orc_step(const orc_grid *G, double *f, double *g, double *fs, double *gs, int64_t nsteps)
 {
     lat_t L;
     if (make_lat(G, &L)) return -1;
+    if (G->fd_courant < 0.0) return -3;
+    if (G->fd_courant > 0.0) {
+        if (G->tau <= 0.0) return -2;
+        for (int64_t s = 0; s < nsteps; ++s) one_step_fd(G, &L, f, g, fs, gs);
+        return 0;
+    }
     if (G->tau <= 0.5) return -2;
     for (int64_t s = 0; s < nsteps; ++s) one_step(G, &L, f, g, fs, gs);
     return 0;
