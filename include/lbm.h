@@ -153,6 +153,22 @@ lbm_status lbm_set_graphs(lbm_sim sim, int32_t enable);
  * LBM_EUNSUPPORTED (enable on an open axis or in 3-D). */
 lbm_status lbm_set_inplace(lbm_sim sim, int32_t enable);
 
+/* Update of the translational populations, chosen before the first step.
+ * courant = 0 (default): collide and stream (exact shift by the integer
+ * lattice velocity; time step dx / r).  0 < courant <= 1: the
+ * finite-difference form of Sec. V A for f as well as g -- forward Euler in
+ * time, third-order upwind in space, BGK -- with time step courant * dx / r,
+ * so population i moves with Courant number courant * c_i per axis; tau
+ * stays in units of dx / r (collision rate courant / tau per step).  The
+ * scheme amplifies some mode at every step size (weakly below courant ~
+ * 1/6, by > 4x per step at courant = 1 for |c| = 3); the collisions keep
+ * e.g. the Sec. VI tube bounded at courant <= 0.2.  1-D and 2-D grids
+ * (D1Q7, D2Q49, D2Q37), ping-pong (in-place streaming off); no conservation
+ * monitor; each lbm_step advances steps of courant * dx / r.  Errors:
+ * LBM_EINVAL (after the first step, courant outside [0, 1]),
+ * LBM_EUNSUPPORTED (3-D). */
+lbm_status lbm_set_fd(lbm_sim sim, double courant);
+
 /* Order of the translational values inside f[0], f[1], chosen before the
  * first step.  enable = 0: plain [Q][N] (slot i of node x at i*N + x).
  * enable = 1 (3-D grids with n0 a multiple of 64): blocks of 64 x-consecutive

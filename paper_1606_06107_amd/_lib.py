@@ -56,6 +56,7 @@ SIGNATURES = {
     "lbm_set_tile": (c_i32, [c_vp, c_i32, c_i32, c_i32]),
     "lbm_set_inplace": (c_i32, [c_vp, c_i32]),
     "lbm_set_blocked": (c_i32, [c_vp, c_i32]),
+    "lbm_set_fd": (c_i32, [c_vp, ctypes.c_double]),
     "lbm_destroy": (c_i32, [c_vp]),
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_lattice_info": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl), c_vp, c_vp]),

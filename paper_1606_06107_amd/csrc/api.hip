@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "fd.hpp"
 #include "launch.hpp"
 #include "lbm.h"
 #include "lbm_device.hpp"
@@ -128,6 +129,7 @@ struct lbm_sim_s {
     int layout = lbmx::kLayoutStreamed;   // what f[fcur] holds (just initialised)
     int inplace = 0;                      // translational streaming in one buffer
     int blocked = 0;                      // value order of f (lbmx::pop_index)
+    double fd = 0.0;                      // > 0: finite-difference update, this Courant factor
     int64_t t = 0;
     int tile[3];
     int graphs = 1;
@@ -156,7 +158,10 @@ int64_t N_of(const lbm_desc &d) { return d.n[0] * d.n[1] * d.n[2]; }
 void advance(lbm_sim s, int64_t n) {
     if (n <= 0) return;
     s->gcur = (int)((s->gcur + n) & 1);
-    if (s->inplace) {
+    if (s->fd > 0.0) {  // values stay at their nodes
+        s->fcur = (int)((s->fcur + n) & 1);
+        s->layout = lbmx::kLayoutStreamed;
+    } else if (s->inplace) {
         // even steps turn kLayoutStreamed into kLayoutSwapped, odd steps back
         if (n & 1)
             s->layout = s->layout == lbmx::kLayoutStreamed ? lbmx::kLayoutSwapped : lbmx::kLayoutStreamed;
@@ -166,8 +171,36 @@ void advance(lbm_sim s, int64_t n) {
     }
 }
 
+// Enqueue one finite-difference time step (lbm_set_fd).
+hipError_t enqueue_step_fd(lbm_sim s, hipStream_t st) {
+    const lbm_desc &d = s->d;
+    lbmx::FdArgs a;
+    a.f_in = d.f[s->fcur];
+    a.g_in = d.g[s->gcur];
+    a.f_out = d.f[s->fcur ^ 1];
+    a.g_out = d.g[s->gcur ^ 1];
+    a.n0 = (int)d.n[0];
+    a.n1 = (int)d.n[1];
+    a.open0 = d.bc[0] == LBM_BC_OPEN;
+    a.open1 = d.dim >= 2 && d.bc[1] == LBM_BC_OPEN;
+    a.N = (uint32_t)N_of(d);
+    a.lambda = s->fd;
+    a.omega = s->fd / d.tau;
+    a.n_rot = d.n_rot;
+    int tx, ty;
+    lbmx::fd_tile(d.dim, &tx, &ty);
+    a.tiles0 = (a.n0 + tx - 1) / tx;
+    a.ntiles = a.tiles0 * (d.dim >= 2 ? (a.n1 + ty - 1) / ty : 1);
+    hipError_t e = lbmx::launch_step_fd(d.dtype, d.dim, kind_of(d.lattice), a, st);
+    if (e != hipSuccess) return e;
+    advance(s, 1);
+    s->t += 1;
+    return hipSuccess;
+}
+
 // Enqueue one time step on stream st and advance the host-side state.
 hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
+    if (s->fd > 0.0) return enqueue_step_fd(s, st);
     const lbm_desc &d = s->d;
     lbmx::StepArgs a;
     a.f_in = d.f[s->fcur];
@@ -316,6 +349,8 @@ lbm_status lbm_step(lbm_sim s, int64_t nsteps) {
     if (!s) return fail(LBM_EINVAL, "sim is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return LBM_OK;
+    if (s->fd > 0.0 && s->mon_every > 0)
+        return fail(LBM_EUNSUPPORTED, "the conservation monitor is not available with the finite-difference update");
     if (!s->graphs || nsteps == 1) {
         for (int64_t k = 0; k < nsteps; ++k) {
             hipError_t e = enqueue_step(s, s->stream);
@@ -434,7 +469,23 @@ lbm_status lbm_set_inplace(lbm_sim s, int32_t enable) {
         return fail(LBM_EINVAL, "the streaming scheme can only be chosen before the first step");
     if (enable && !inplace_possible(s->d))
         return fail(LBM_EUNSUPPORTED, "in-place streaming needs a 1-D or 2-D grid periodic in every axis");
+    if (enable && s->fd > 0.0)
+        return fail(LBM_EUNSUPPORTED, "the finite-difference update ping-pongs");
     s->inplace = enable ? 1 : 0;
+    clear_cache(s);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_fd(lbm_sim s, double courant) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (s->t != 0 || s->layout != lbmx::kLayoutStreamed)
+        return fail(LBM_EINVAL, "the update can only be chosen before the first step");
+    if (!(courant >= 0.0 && courant <= 1.0)) return fail(LBM_EINVAL, "courant must be in [0, 1]");
+    if (courant > 0.0 && s->d.dim > 2)
+        return fail(LBM_EUNSUPPORTED, "the finite-difference update runs on 1-D and 2-D grids");
+    s->fd = courant;
+    if (courant > 0.0) s->inplace = 0;
+    else s->inplace = inplace_possible(s->d) ? 1 : 0;
     clear_cache(s);
     return LBM_OK;
 }

@@ -93,8 +93,11 @@ class Sim:
         self._graphs = None
         self._inplace = None
         self._blocked = None
+        self._fd = None
 
     def _apply_settings(self):
+        if self._fd is not None:  # first: it decides the streaming scheme
+            L.check(self.lib.lbm_set_fd(self.handle, float(self._fd)))
         if self._blocked is not None:  # first: enabling it resets the tile
             L.check(self.lib.lbm_set_blocked(self.handle, 1 if self._blocked else 0))
         if self._tile is not None:
@@ -151,6 +154,14 @@ class Sim:
         grids."""
         L.check(self.lib.lbm_set_inplace(self.handle, 1 if on else 0))
         self._inplace = bool(on)
+        return self
+
+    def set_fd(self, courant: float):
+        """Finite-difference update of Sec. V A for f as well (courant in
+        (0, 1]: time step courant * dx / r), or collide-and-stream (0, the
+        default); only before the first step.  1-D and 2-D grids."""
+        L.check(self.lib.lbm_set_fd(self.handle, float(courant)))
+        self._fd = float(courant)
         return self
 
     def set_blocked(self, on: bool):
