@@ -202,6 +202,37 @@ def extra_d2q37(steps=200):
             "sec6_tube_1000x16_fp64_180_steps_ms": round(ms_tube, 3)}
 
 
+def extra_fd(steps=200, courant=0.05):
+    """The finite-difference update of Sec. V A (lbm_set_fd) on the 1024^2
+    periodic workload, D2Q49 + D1Q7 FP32, Courant factor 0.05 (the largest
+    that keeps these fields bounded at tau = 1; the speed does not depend on
+    it): each step
+    reads every population at its node plus three upwind neighbours per
+    axis it moves along (cached) and writes it once."""
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    w = workloads.Periodic2D()
+    sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields()).set_fd(courant)
+    sim.step(steps)  # capture + warm
+    sim.init(*w.fields())
+    a, b = _events(sim.stream)
+    torch.cuda.synchronize()
+    a.record(sim.stream)
+    sim.step(steps)
+    b.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    N = w.nx * w.ny
+    gbs = N * 448 / (ms * 1e-3) / 1e9
+    T = sim.moments(totals=False)[2]
+    ok = bool(torch.isfinite(T).all().item())
+    return {"workload": "2-D periodic 1024x1024, D2Q49+D1Q7 FP32, finite-difference update, Courant factor 0.05",
+            "ms_per_step": round(ms, 4), "MLUPS": round(N / ms / 1e3, 1), "GBps_algorithmic": round(gbs, 1),
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok}
+
+
 def extra_batch(seed=0):
     """4096 ragged shock tubes, one persistent launch, FP32 and FP64, with the
     per-instance FP32-vs-FP64 relative L1 error of rho, u, T (Sec. VI)."""
@@ -333,7 +364,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,d2q37,batched_tubes,surrogate",
+    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,d2q37,fd,batched_tubes,surrogate",
                     help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ping-pong", action="store_true",
@@ -440,7 +471,7 @@ def main():
         extra = {}
         wanted = set(args.extras.split(","))
         for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d), ("d2q37", extra_d2q37),
-                         ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
+                         ("fd", extra_fd), ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
             if name not in wanted:
                 continue
             print(f"bench: {name}", file=sys.stderr, flush=True)
