@@ -233,6 +233,28 @@ def extra_fd(steps=200, courant=0.05):
             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok}
 
 
+def extra_transport(tau=0.8, n_values=(0.0, 2.0, 4.0, 6.0)):
+    """Shear viscosity and heat diffusivity measured on the GPU (decaying
+    Fourier modes, D2Q49 FP64, 64 x 3 periodic) against the Chapman-Enskog
+    results: nu = (T/r^2)(tau - 1/2); the paper's kappa implies chi = nu
+    (Pr = 1), while only the translational populations carry heat in the
+    scheme (chi = (D+2)/(D+n+2) nu)."""
+    import torch
+
+    from paper_1606_06107_amd import lattice_info, transport
+    r = lattice_info(1)[1]
+    nu_th = (tau - 0.5) / r ** 2
+    rows = []
+    for n in n_values:
+        nu = transport.shear_viscosity(n, tau, dtype=torch.float64)
+        chi = transport.thermal_diffusivity(n, tau, dtype=torch.float64)
+        rows.append({"n": n, "nu": round(nu, 6), "nu_over_theory": round(nu / nu_th, 5), "chi": round(chi, 6),
+                     "Pr_measured": round(nu / chi, 4), "Pr_translational_heat_flux": round((n + 4) / 4, 4),
+                     "Pr_paper_CE": 1.0})
+    return {"workload": "shear and isobaric temperature waves, 64x3 periodic, D2Q49+D1Q7 FP64, tau=0.8, T=1",
+            "nu_theory": round(nu_th, 6), "rows": rows}
+
+
 def extra_batch(seed=0):
     """4096 ragged shock tubes, one persistent launch, FP32 and FP64, with the
     per-instance FP32-vs-FP64 relative L1 error of rho, u, T (Sec. VI)."""
@@ -364,7 +386,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,d2q37,fd,batched_tubes,surrogate",
+    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,d2q37,fd,transport,batched_tubes,surrogate",
                     help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ping-pong", action="store_true",
@@ -471,7 +493,8 @@ def main():
         extra = {}
         wanted = set(args.extras.split(","))
         for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d), ("d2q37", extra_d2q37),
-                         ("fd", extra_fd), ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
+                         ("fd", extra_fd),
+                         ("transport", extra_transport), ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
             if name not in wanted:
                 continue
             print(f"bench: {name}", file=sys.stderr, flush=True)

@@ -106,3 +106,30 @@ def test_paper_worked_example_table3(orc):
     table = {k: float(v) for k, v in golden("table3_errors.txt")}
     for k, v in table.items():
         assert v / 2.0 <= e[k] <= 2.0 * v, (k, e[k], v)
+
+
+@pytest.mark.parametrize("n_rot", [0.0, 2.0, 6.0])
+def test_heat_diffusivity_translational_only(orc, n_rot):
+    # An isobaric temperature wave (rho T = const, u = 0) decays as
+    # exp(-chi k^2 t).  Only the translational populations move relative to
+    # the fluid (the rotational ones are advected with u), so the heat flux
+    # is that of the D+2 translational degrees of freedom while the heat
+    # capacity counts all D+n+2: chi = (D+2)/(D+n+2) (T/r^2)(tau - 1/2),
+    # i.e. (D+2)/(D+n+2) of the conductivity of the paper's Chapman-Enskog
+    # result (Sec. II), whose Prandtl number is 1.
+    L, tau, T0, eps, D = 64, 0.8, 1.0, 0.01, 2
+    G = orc.Grid(orc.D2Q49, (L, 3), n_rot=n_rot, tau=tau)
+    x = np.tile(np.arange(L), 3)
+    k = 2 * np.pi / L
+    s = np.sin(k * x)
+    f, g = G.init_eq(1 / (1 + eps * s), np.zeros((2, 3 * L)), T0 * (1 + eps * s))
+    amps = []
+    for _ in range(6):
+        G.step(f, g, 100)
+        amps.append(2 * abs(np.mean(G.moments(f, g)[2] * np.exp(-1j * k * x))))
+    t = 100 * np.arange(1, 7)
+    chi = -np.polyfit(t[2:], np.log(amps[2:]), 1)[0] / k ** 2
+    nu = T0 / orc.d1q7_r() ** 2 * (tau - 0.5)
+    assert chi == pytest.approx((D + 2) / (D + n_rot + 2) * nu, rel=4e-2)
+    if n_rot > 0:
+        assert abs(chi / nu - 1.0) > 0.3  # not the paper's Pr = 1
