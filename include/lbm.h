@@ -185,7 +185,8 @@ lbm_status lbm_set_blocked(lbm_sim sim, int32_t enable);
 /* Launch shape of the step kernel: nodes per workgroup tile along x, y, z
  * (product 64..1024, a multiple of 64; tile_x a multiple of 16).  Used by the
  * autotuner; results do not depend on it.  LBM_EUNSUPPORTED if the shape is
- * not compiled, or not 64x1x1 under the blocked order. */
+ * not compiled, or not 64x1x1 under the blocked order.  (The finite-difference
+ * update of lbm_set_fd runs with its own fixed shape.) */
 lbm_status lbm_set_tile(lbm_sim sim, int32_t tx, int32_t ty, int32_t tz);
 
 /* Release the handle and its graphs (NULL-safe).  Device buffers are the
