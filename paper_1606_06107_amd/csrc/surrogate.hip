@@ -39,21 +39,28 @@ constexpr int B_KC = 0, B_BC = 320, B_W1 = 384, B_B1 = 8576, B_W2 = 8704, B_B2 =
 constexpr int P_WH = P_BLK + NB * BLK, P_BH = P_WH + FOUT * C, NPARAMS = P_BH + FOUT;
 static_assert(NPARAMS == LBM_SUR_NPARAMS, "parameter count");
 // BF16 copies (element offsets)
-constexpr int Q_WE = 0, Q_BLK = 1024, QBLK = 40960;  // per block: W1, W1t, W2, W2t, W2p
-constexpr int Q_W1 = 0, Q_W1T = 8192, Q_W2 = 16384, Q_W2T = 24576, Q_W2P = 32768;
+constexpr int Q_WE = 0, Q_BLK = 1024, QBLK = 49152;  // per block: W1, W1t, W2, W2t, W2f, W1f
+constexpr int Q_W1 = 0, Q_W1T = 8192, Q_W2 = 16384, Q_W2T = 24576, Q_W2F = 32768, Q_W1F = 40960;
 constexpr int Q_WHP = Q_BLK + NB * QBLK;   // [32][64], rows >= 12 zero
 constexpr int Q_WHTP = Q_WHP + 32 * C;     // [64][16], cols >= 12 zero
 constexpr int QTOTAL = Q_WHTP + C * 16;
 
-// Fragment order of the second MLP product in the fused forward kernel: the
+// Hidden order of the second MLP product in the fused forward kernel: the
 // output of the first product (hidden x tokens) leaves lane half h holding,
 // within each 16-wide hidden chunk, offsets {4h..4h+3, 8+4h..8+4h+3}; used
 // directly as the A operand, its k slot 8h + e therefore means hidden offset
-// 4h + e (+4 for e >= 4).  W2p stores W2 with its hidden index in that order.
+// 4h + e (+4 for e >= 4).
 __host__ __device__ constexpr int w2p_hidden(int kk) {
     const int q = kk / 16, s = kk % 16, h = s / 8, e = s % 8;
     return 16 * q + 4 * h + e + (e >= 4 ? 4 : 0);
 }
+// The fused forward kernel's weight operands in fragment order: fragment f
+// is 64 lanes x 8 BF16 = 1 KB contiguous, lane l at 16 l bytes, so that each
+// operand load of a wave reads whole cache lines.
+//   W1f  fragment 4 h + s (hidden tile h, k step s): lane 32 hl + n holds
+//        W1[32 h + n][16 s + 8 hl .. +7]
+//   W2f  fragment 2 q + o (hidden chunk q, output tile o): lane 32 hl + n
+//        holds W2[32 o + n][w2p_hidden(16 q + 8 hl + e)], e = 0..7
 
 // Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
 __device__ __forceinline__ __bf16 to_bf16(float f) {
@@ -403,10 +410,15 @@ __global__ void __launch_bounds__(256) k_pack(const float *P, __bf16 *Q) {
         else if (r < Q_W2) { const int i = r - Q_W1T, k = i / HID, n = i % HID;  // W1t [64][128]
             v = blk[B_W1 + n * C + k]; }
         else if (r < Q_W2T) v = blk[B_W2 + (r - Q_W2)];                          // W2 [64][128]
-        else if (r < Q_W2P) { const int i = r - Q_W2T, k = i / C, n = i % C;     // W2t [128][64]
+        else if (r < Q_W2F) { const int i = r - Q_W2T, k = i / C, n = i % C;     // W2t [128][64]
             v = blk[B_W2 + n * HID + k]; }
-        else { const int i = r - Q_W2P, n = i / HID, kk = i % HID;               // W2p [64][128]
-            v = blk[B_W2 + n * HID + w2p_hidden(kk)]; }
+        else {                                                                   // W2f, W1f
+            const bool w1 = r >= Q_W1F;
+            const int i = r - (w1 ? Q_W1F : Q_W2F), f = i / 512, ln = (i / 8) % 64, e = i % 8;
+            const int n = ln % 32, hl = ln / 32;
+            if (w1) v = blk[B_W1 + (32 * (f / 4) + n) * C + 16 * (f % 4) + 8 * hl + e];
+            else v = blk[B_W2 + (32 * (f % 2) + n) * HID + w2p_hidden(16 * (f / 2) + 8 * hl + e)];
+        }
     } else if (e < Q_WHTP) {
         const int i = e - Q_WHP, n = i / C, k = i % C;                           // Whp [32][64]
         v = n < FOUT ? P[P_WH + n * C + k] : 0.0f;
@@ -433,20 +445,21 @@ __global__ void __launch_bounds__(256) k_adam(int n, float *p, float *m, float *
 // ---------------------------------------------------------------------------
 // Fused inference: one workgroup (4 waves) carries a tile of 128 consecutive
 // tokens of one tube through the embedding, the four blocks and the head,
-// with the residual stream in LDS (FP32) and the convolution output in LDS
-// (BF16).  Each block's depthwise convolution needs two tokens on each side,
-// so the tile carries 8 halo tokens per side and writes the middle 112.
+// with the residual stream in LDS (FP32, 35 KB).  Each block's depthwise
+// convolution needs two tokens on each side, so the tile carries 8 halo
+// tokens per side and writes the middle 112.
 // Wave w owns rows 32w..32w+31.  The first MLP product is formed transposed,
-// Z1^T = W1 Hc^T, so that each lane's accumulators (one token, 16 hidden
-// units) become, after bias, GELU and BF16 rounding, the A operand of the
-// second product in registers (hidden order as in W2p).  Rounding points
-// are those of the layer-wise kernels: the inputs, Hc, GELU(Z1) and H4.
+// Z1^T = W1 Hc^T, one 32-wide hidden tile at a time, so that each lane's
+// accumulators (one token, 16 hidden units) become, after bias, GELU and
+// BF16 rounding, the A operand of the second product in registers (hidden
+// order as in W2f); at most 168 registers per lane keep three waves on each
+// SIMD.  Rounding points are those of the layer-wise kernels: the inputs,
+// Hc, GELU(Z1) and H4.
 // ---------------------------------------------------------------------------
 constexpr int FR = 128;                 // token rows per tile
 constexpr int FHALO = 2 * NB;           // halo rows per side
 constexpr int FOUTR = FR - 2 * FHALO;   // output rows per tile
 constexpr int HS = C + 4;               // FP32 row stride in LDS
-constexpr int BS = C + 8;               // BF16 row stride in LDS
 
 struct FwdArgs {
     int B, L, T, ntile;
@@ -469,9 +482,22 @@ __device__ __forceinline__ bf16x8 ld_frag(const __bf16 *p) {
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-__global__ void __launch_bounds__(256) k_fwd_fused(FwdArgs a) {
-    __shared__ __attribute__((aligned(16))) float Hf[FR * HS];
-    __shared__ __attribute__((aligned(16))) __bf16 Hb[FR * BS];
+// Eight BF16 of the FP32 row p[0..7] (an MFMA operand fragment).
+__device__ __forceinline__ bf16x8 frag_from_f32(const float *p) {
+    const float4 u = *reinterpret_cast<const float4 *>(p);
+    const float4 v = *reinterpret_cast<const float4 *>(p + 4);
+    bf16x8 f;
+    f[0] = (__bf16)u.x; f[1] = (__bf16)u.y; f[2] = (__bf16)u.z; f[3] = (__bf16)u.w;
+    f[4] = (__bf16)v.x; f[5] = (__bf16)v.y; f[6] = (__bf16)v.z; f[7] = (__bf16)v.w;
+    return f;
+}
+
+__global__ void __launch_bounds__(256, 3) k_fwd_fused(FwdArgs a) {
+    // Rows -2, -1, FR and FR + 1 stay zero: the convolution window of the
+    // edge rows reads them unconditionally.
+    __shared__ __attribute__((aligned(16))) float Hs[(FR + 4) * HS];
+    float *const Hf = Hs + 2 * HS;
+    for (int e = threadIdx.x; e < 4 * HS; e += 256) Hs[e < 2 * HS ? e : (FR + 2) * HS + e - 2 * HS] = 0.0f;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, n32 = l & 31, hl = l >> 5;
     const int b = blockIdx.x / a.ntile, tile = blockIdx.x % a.ntile;
     const int t0 = tile * FOUTR - FHALO;  // token of row 0
@@ -521,8 +547,7 @@ __global__ void __launch_bounds__(256) k_fwd_fused(FwdArgs a) {
             float win[36];
 #pragma unroll
             for (int m = 0; m < 36; ++m) {
-                const int r = r0 + m - 2;
-                win[m] = (r >= 0 && r < FR) ? Hf[r * HS + c] : 0.0f;
+                win[m] = Hf[(r0 + m - 2) * HS + c];
             }
 #pragma unroll
             for (int m = 0; m < 32; ++m) {
@@ -534,50 +559,37 @@ __global__ void __launch_bounds__(256) k_fwd_fused(FwdArgs a) {
         }
         __syncthreads();  // every read of H done
 #pragma unroll
-        for (int m = 0; m < 32; ++m) {
-            Hf[(r0 + m) * HS + l] = hc[m];
-            Hb[(r0 + m) * BS + l] = (__bf16)hc[m];
-        }
-        // MLP on the wave's rows.
-        bf16x8 hb[4];  // B operand of Z1^T: token n32, channels 16 s + 8 hl ..
+        for (int m = 0; m < 32; ++m) Hf[(r0 + m) * HS + l] = hc[m];
+        // MLP on the wave's rows.  B operand of Z1^T: token n32, channels
+        // 16 s + 8 hl .. +7, rounded from the rows the wave just wrote.
+        bf16x8 hb[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) hb[s] = ld_frag(&Hb[(r0 + n32) * BS + 16 * s + 8 * hl]);
+        for (int s = 0; s < 4; ++s) hb[s] = frag_from_f32(&Hf[(r0 + n32) * HS + 16 * s + 8 * hl]);
         f32x16 acc2[2];
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot)
             for (int i = 0; i < 16; ++i) acc2[ot][i] = 0.0f;
 #pragma unroll
-        for (int hp = 0; hp < 2; ++hp) {  // pairs of 32-wide hidden tiles
-            f32x16 acc1[2];
+        for (int h = 0; h < 4; ++h) {  // 32-wide hidden tiles
+            // The tile's eight weight fragments, issued together.
+            bf16x8 w1[4], w2[4];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int h = 2 * hp + u;
+            for (int s = 0; s < 4; ++s) w1[s] = ld_frag(qb + Q_W1F + (4 * h + s) * 512 + 8 * l);
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    acc1[u][i] = blk[B_B1 + 32 * h + 8 * (i >> 2) + 4 * hl + (i & 3)];
-            }
+            for (int f = 0; f < 4; ++f) w2[f] = ld_frag(qb + Q_W2F + (4 * h + f) * 512 + 8 * l);
+            f32x16 acc1;
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int i = 0; i < 16; ++i) acc1[i] = blk[B_B1 + 32 * h + 8 * (i >> 2) + 4 * hl + (i & 3)];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int h = 2 * hp + u;
-                    acc1[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        ld_frag(qb + Q_W1 + (32 * h + n32) * C + 16 * s + 8 * hl), hb[s], acc1[u], 0, 0, 0);
-                }
+            for (int s = 0; s < 4; ++s) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[s], hb[s], acc1, 0, 0, 0);
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int h = 2 * hp + u;
+            for (int cc = 0; cc < 2; ++cc) {  // 16-wide hidden chunk 2 h + cc
+                bf16x8 af;
 #pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
-                    bf16x8 af;
+                for (int e = 0; e < 8; ++e) af[e] = (__bf16)gelu_fast(acc1[8 * cc + e]);
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) af[e] = (__bf16)gelu_fast(acc1[u][8 * cc + e]);
-                    const int q = 2 * h + cc;  // 16-wide hidden chunk
-#pragma unroll
-                    for (int ot = 0; ot < 2; ++ot)
-                        acc2[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            af, ld_frag(qb + Q_W2P + (32 * ot + n32) * HID + 16 * q + 8 * hl), acc2[ot], 0, 0, 0);
-                }
+                for (int ot = 0; ot < 2; ++ot)
+                    acc2[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, w2[2 * cc + ot], acc2[ot], 0, 0, 0);
             }
         }
         // H' = Hc + A1 W2^T + b2 on the wave's rows (zero outside the tube).
@@ -585,11 +597,13 @@ __global__ void __launch_bounds__(256) k_fwd_fused(FwdArgs a) {
         for (int ot = 0; ot < 2; ++ot) {
             const int ch = 32 * ot + n32;
             const float b2 = blk[B_B2 + ch];
+            float hv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) hv[i] = Hf[(r0 + 8 * (i >> 2) + 4 * hl + (i & 3)) * HS + ch];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
-                const float v = Hf[r * HS + ch] + acc2[ot][i] + b2;
-                Hf[r * HS + ch] = in_tube(r) ? v : 0.0f;
+                Hf[r * HS + ch] = in_tube(r) ? hv[i] + acc2[ot][i] + b2 : 0.0f;
             }
         }
     }
@@ -599,10 +613,7 @@ __global__ void __launch_bounds__(256) k_fwd_fused(FwdArgs a) {
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const float *hr = &Hf[(r0 + n32) * HS + 16 * s + 8 * hl];
-        bf16x8 ha;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) ha[e] = (__bf16)hr[e];
+        const bf16x8 ha = frag_from_f32(&Hf[(r0 + n32) * HS + 16 * s + 8 * hl]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha, ld_frag(a.Q + Q_WHP + n32 * C + 16 * s + 8 * hl), acc, 0,
                                                       0, 0);
     }

@@ -113,7 +113,7 @@ def test_workspace_sizes(lib):
     bd = lib.LbmBatchDesc()
     bd.abi_version, bd.num_instances = lib.LBM_ABI_VERSION, 4096
     assert L.lbm_batch_workspace_bytes(ctypes.byref(bd)) >= 4096 * 4
-    assert L.lbm_sur_bf16_bytes() == 2 * (1024 + 4 * 40960 + 32 * 64 + 64 * 16)
+    assert L.lbm_sur_bf16_bytes() == 2 * (1024 + 4 * 49152 + 32 * 64 + 64 * 16)
     sd = lib.LbmSurDesc()
     sd.abi_version, sd.batch, sd.length = lib.LBM_ABI_VERSION, 2, 256
     assert L.lbm_sur_workspace_bytes(ctypes.byref(sd)) > 2 * 64 * 64 * 4 * 9
