@@ -360,6 +360,18 @@ def extra_surrogate(train_candidates=8192, test_candidates=2048, train_steps=300
     one.init(te.rho, te.u[0], te.T).step()
     err_one = l1(surB.forward(x0, gamma), SG.fields_of(one))
     err_one_id = l1(x0, SG.fields_of(one))
+    # the fused forward alone: 134.7 kFLOP of matrix products per output token
+    y = torch.empty_like(x0)
+    reps = 20
+    a, e = _events(surB.stream)
+    torch.cuda.synchronize()
+    a.record(surB.stream)
+    for _ in range(reps):
+        surB.forward(x0, gamma, y)
+    e.record(surB.stream)
+    torch.cuda.synchronize()
+    t_fwd = a.elapsed_time(e) / reps
+    fwd_flop = 2.0 * (16 * 64 + 4 * 2 * 64 * 128 + 64 * 12) * B * 1024
     accepted = int(acc.sum().item())
     return {"workload": f"{B} held-out stable 4096-node tubes, {calls} calls x 16 steps",
             "train": {"stable_tubes": int(bt.num), "pairs": int(bt.num * pairs_per_tube),
@@ -367,6 +379,9 @@ def extra_surrogate(train_candidates=8192, test_candidates=2048, train_steps=300
                       "seconds": round(t_train, 2), "loss": hist},
             "t_lbm_ms": round(t_lbm, 3), "t_surrogate_with_fallback_ms": round(t_sur, 3),
             "speedup": round(t_lbm / t_sur, 3), "accepted_fraction": round(accepted / (B * calls), 4),
+            "forward_ms": round(t_fwd, 4),
+            "forward_mfma": {"achieved": round(fwd_flop / t_fwd / 1e9, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                             "frac": round(fwd_flop / t_fwd / 1e9 / 2500.0, 4)},
             "rel_l1_rho_u_T": [round(float(v), 5) for v in err],
             "rel_l1_no_fallback": [round(float(v), 5) for v in err_nf],
             "rel_l1_identity": [round(float(v), 5) for v in err_id],
