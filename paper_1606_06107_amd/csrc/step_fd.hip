@@ -44,19 +44,18 @@ __global__ void __launch_bounds__(TX *TY) k_step_fd(FdArgs a) {
     const char *fin = static_cast<const char *>(a.f_in);
     const char *gin = static_cast<const char *>(a.g_in);
 
-    P fv[Q], gv[7];
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        fv[i] = ld<P>(fin + i * PS, nodeb);
-    });
+    // FP64 moments from per-column (c_x) and per-row (c_y) sums.  The
+    // populations are not kept: each is read again (a cache hit) where it is
+    // updated, which keeps the register count, and so the occupancy, of this
+    // load-heavy kernel down (175 -> 113 registers in 2-D FP32).  Staging the
+    // population planes through LDS measured slower than these cached reads.
+    P gv[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) gv[j] = ld<P>(gin + j * PS, nodeb);
-
-    // FP64 moments from per-column (c_x) and per-row (c_y) sums.
     double col[7] = {0, 0, 0, 0, 0, 0, 0}, row[7] = {0, 0, 0, 0, 0, 0, 0};
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value, d = L::dir(i);
-        const double v = (double)fv[i];
+        const double v = (double)ld<P>(fin + i * PS, nodeb);
         col[cx_of(d) + 3] += v;
         if constexpr (D >= 2) row[cy_of(d) + 3] += v;
     });
@@ -88,7 +87,7 @@ __global__ void __launch_bounds__(TX *TY) k_step_fd(FdArgs a) {
         constexpr int i = decltype(I)::value, d = L::dir(i);
         constexpr int cx = cx_of(d), cy = cy_of(d);
         const char *fi = fin + i * PS;
-        const P f0 = fv[i];
+        const P f0 = ld<P>(fi, nodeb);
         P adv = P(0);
         if constexpr (cx > 0)
             adv += (lam * P(cx)) * ((ld<P>(fi, ox[0]) - P(6) * ld<P>(fi, ox[1]) + P(3) * f0 +
