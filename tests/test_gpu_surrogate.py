@@ -69,10 +69,36 @@ def test_forward_matches_reference(torch_cuda, B, L):
     assert err <= FWD_TOL
 
 
-def test_backward_matches_reference(torch_cuda):
-    announce("surrogate backward")
-    p, x, gamma, target = _problem(1)
-    B, L = x.shape[1], x.shape[2]
+def test_forward_full_size_sampled(torch_cuda):
+    """The inference launch the benchmark times: 173 tubes x 4096 nodes
+    (1730 tiles) in one call, checked against the reference on sampled tubes
+    (first, last, interior); each tube's result is bitwise that of a launch
+    over that tube alone (no dependence on the batch around it)."""
+    B, L = 173, 4096
+    announce(f"surrogate forward full size B={B} L={L}")
+    p, x, gamma, _ = _problem(seed=3, B=B, L=L)
+    sur = _gpu(torch_cuda, p, B, L)
+    y = sur.forward(_dev(torch_cuda, x), _dev(torch_cuda, gamma)).cpu().numpy()
+    assert np.isfinite(y).all()
+    pf = S.unpack(p.astype(np.float32).astype(np.float64))
+    for b in (0, 1, 86, 171, 172):
+        y_ref, _ = S.forward(pf, x[:, b:b + 1], gamma[b:b + 1], rounded=True)
+        dy_ref, dy = (y_ref[:, 0] - x[:, b]) / 0.1, (y[:, b] - x[:, b]) / 0.1
+        err = np.abs(dy - dy_ref).max() / np.abs(dy_ref).max()
+        print(f"tube {b}: max error / max |Y| = {err:.2e}", flush=True)
+        assert err <= FWD_TOL
+    one = _gpu(torch_cuda, p, 1, L)
+    for b in (0, 86, 172):
+        y1 = one.forward(_dev(torch_cuda, x[:, b:b + 1]), _dev(torch_cuda, gamma[b:b + 1])).cpu().numpy()
+        assert np.array_equal(y1[:, 0], y[:, b])
+
+
+@pytest.mark.parametrize("B,L", [(2, 256), (32, 4096)])
+def test_backward_matches_reference(torch_cuda, B, L):
+    """Loss and every parameter gradient; (32, 4096) is the training batch
+    (32,768 tokens: 256 row chunks in the weight-gradient reductions)."""
+    announce(f"surrogate backward B={B} L={L}")
+    p, x, gamma, target = _problem(1, B=B, L=L)
     sur = _gpu(torch_cuda, p, B, L)
     pf = S.unpack(p.astype(np.float32).astype(np.float64))
     loss_ref, g_ref, _ = S.loss_and_grads(pf, x, gamma, target, rounded=True)
