@@ -321,10 +321,14 @@ lbm_status lbm_sur_adam(const lbm_sur_desc *desc, float *params, float *m, float
                         int64_t step, void *hip_stream);
 
 /* Admission check of a surrogate step for every tube b: with n_b from
- * gamma_b (n = 2/(gamma-1) - 1), the totals mass = sum rho, momentum =
- * sum rho u and energy = sum rho (u^2/2 + (1+n) T/2) of y must match those
- * of x within tol_mass, tol_mom (relative to mass * sqrt(max T)) and
- * tol_energy (relative), and y must be finite with rho > 0 and T > 0.
+ * gamma_b (n = 2/(gamma-1) - 1), the change from x to y of the totals
+ * mass = sum rho, momentum = sum rho u and energy = sum rho (u^2/2 +
+ * (1+n) T/2) must equal what crosses the tube's open ends in LBM_SUR_K
+ * steps (the balance laws of Sec. II: (K/r) times the difference of the
+ * equilibrium fluxes rho u, rho (u^2 + T), rho u (u^2/2 + (3+n) T/2) at the
+ * first and last node, end states averaged over x and y) within tol_mass,
+ * tol_mom (relative to mass * sqrt(max T of x)) and tol_energy (relative),
+ * and y must be finite with rho > 0 and T > 0.
  * accept[b] = 1 or 0 (device int32).  The totals use FP64 and a fixed
  * reduction order. */
 lbm_status lbm_sur_check(const lbm_sur_desc *desc, const double *x, const double *y,

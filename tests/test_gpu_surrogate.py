@@ -136,6 +136,10 @@ def test_check_lift_merge(torch_cuda):
     x = np.stack([0.6 + 0.3 * rng.uniform(size=(B, L)), 0.1 * rng.normal(size=(B, L)),
                   0.9 + 0.1 * rng.uniform(size=(B, L))])
     gamma = np.array([1.4, 1.3, 1.6])
+    # ends at rest in the same state: nothing crosses them, so y = x is
+    # admissible for every tube
+    x[1, :, 0] = x[1, :, -1] = 0.0
+    x[0, :, -1], x[2, :, -1] = x[0, :, 0], x[2, :, 0]
     y = x.copy()
     y[0, 1, :] *= 1.01          # tube 1: mass off by 1%
     y[2, 2, 5] = -0.1           # tube 2: negative temperature
@@ -165,6 +169,36 @@ def test_check_lift_merge(torch_cuda):
     o = out.cpu().numpy()
     assert np.array_equal(o[:, 0], y[:, 0]) and np.array_equal(o[:, 1:], 2 * x[:, 1:])
     assert list(sur.valid.cpu().numpy()) == [0, 1, 1]
+
+
+def test_check_accepts_the_plain_scheme(torch_cuda):
+    """The admission check against the plain scheme itself: 16 plain steps
+    of open shock tubes are accepted (their momentum changes by the end
+    pressures' push, their mass and energy stay), and leaving a tube
+    unchanged is rejected exactly when its end pressures differ."""
+    announce("check vs plain scheme")
+    import torch
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd import surrogate as SG
+    L = 512
+    # (rho_l, p_l, rho_r, p_r, gamma)
+    states = [(1.0, 1.0, 0.125, 0.1, 1.4), (1.0, 1.0, 0.5, 0.5, 5.0 / 3.0), (1.0, 1.0, 0.5, 1.0, 1.4)]
+    B = len(states)
+    x = np.zeros((3, B, L))
+    for b, (dl, pl, dr, pr, _) in enumerate(states):
+        left = np.arange(L) < L // 2
+        x[0, b] = np.where(left, dl, dr)
+        x[2, b] = np.where(left, pl / dl, pr / dr)
+    gamma = np.array([s[4] for s in states])
+    n_rot = 2.0 / (gamma - 1.0) - 1.0
+    plain = Batch([L] * B, n_rot, [0.8] * B, [SG.K] * B, dtype=torch.float64)
+    plain.init(x[0].ravel(), x[1].ravel(), x[2].ravel()).step()
+    z = SG.fields_of(plain)
+    assert list(plain.status.cpu().numpy()) == [0] * B
+    sur = _gpu(torch, S.init_params(0), B, L)
+    xd, gd = _dev(torch, x), _dev(torch, gamma)
+    assert list(sur.check(xd, z, gd).cpu().numpy()) == [1, 1, 1]
+    assert list(sur.check(xd, xd, gd).cpu().numpy()) == [0, 0, 1]
 
 
 def test_rejecting_everything_reproduces_plain_lbm_bitwise(torch_cuda):
