@@ -305,8 +305,8 @@ def extra_batch(seed=0):
     return out
 
 
-def extra_surrogate(train_candidates=8192, test_candidates=2048, train_steps=6000, calls=16,
-                    pairs_per_tube=16, train_batch=32, lr=2e-3):
+def extra_surrogate(train_candidates=8192, test_candidates=2048, train_steps=30000, calls=16,
+                    pairs_per_tube=16, train_batch=32, lr=3e-3):
     """Learned surrogate vs plain LBM on held-out 4096-node tubes: 16 calls
     of k = 16 steps (256 steps) from the initial state with the admission
     check and plain-LBM fallback; errors judged against the plain LBM run
@@ -407,6 +407,8 @@ def main():
     ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,d2q37,fd,transport,batched_tubes,surrogate",
                     help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--sur-train-steps", type=int, default=30000,
+                    help="Adam steps of the surrogate extra's training")
     ap.add_argument("--ping-pong", action="store_true",
                     help="two translational buffers instead of in-place streaming")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -512,7 +514,8 @@ def main():
         wanted = set(args.extras.split(","))
         for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d), ("d2q37", extra_d2q37),
                          ("fd", extra_fd),
-                         ("transport", extra_transport), ("batched_tubes", extra_batch), ("surrogate", extra_surrogate)):
+                         ("transport", extra_transport), ("batched_tubes", extra_batch),
+                         ("surrogate", lambda: extra_surrogate(train_steps=args.sur_train_steps))):
             if name not in wanted:
                 continue
             print(f"bench: {name}", file=sys.stderr, flush=True)
