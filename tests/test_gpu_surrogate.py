@@ -224,3 +224,27 @@ def test_rejecting_everything_reproduces_plain_lbm_bitwise(torch_cuda):
     x, acc = rollout(sur, x0, gamma, fb, calls, tols=(-1.0, -1.0, -1.0))
     assert int(acc.sum().item()) == 0
     assert np.array_equal(x.cpu().numpy(), ref)
+
+
+def test_accepting_everything_chains_the_forward_bitwise(torch_cuda):
+    """With a check that accepts every step (the path that skips the fallback
+    launches) the rollout is the surrogate applied `calls` times, bitwise,
+    and the fallback batch is never advanced."""
+    announce("accept all == chained forward")
+    import torch
+    import workloads
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd.surrogate import rollout
+    B, L, calls = 3, 512, 5
+    bt = workloads.batched_tubes(B, seed=3, fixed_length=L, pr_range=(1.5, 3.0), dr_range=(1.0, 2.0))
+    sur = _gpu(torch, S.init_params(0), B, L)
+    x0 = torch.as_tensor(np.stack([bt.rho, bt.u[0], bt.T]).reshape(3, B, L), device="cuda")
+    gamma = torch.as_tensor(bt.gamma, device="cuda")
+    ref = x0.clone()
+    for _ in range(calls):
+        ref = sur.forward(ref, gamma)
+    fb = Batch(bt.lengths, bt.n_rot, bt.tau, np.zeros(B, dtype=np.int64), dtype=torch.float32)
+    x, acc = rollout(sur, x0, gamma, fb, calls, tols=(1e300, 1e300, 1e300))
+    assert acc.cpu().tolist() == [B] * calls
+    assert np.array_equal(x.cpu().numpy(), ref.cpu().numpy())
+    assert int(fb.steps_done.sum().item()) == 0
