@@ -268,11 +268,14 @@ def extra_batch(seed=0):
     (blk, sup), table = tune_batch(
         lambda b_, s_: Batch(bt.lengths, bt.n_rot, bt.tau, bt.steps, block=b_, superstep=s_),
         (bt.rho, bt.u[0], bt.T), key_extra="tubes4096-f32")
+    (blk64, sup64), _ = tune_batch(
+        lambda b_, s_: Batch(bt.lengths, bt.n_rot, bt.tau, bt.steps, dtype=torch.float64, block=b_, superstep=s_),
+        (bt.rho, bt.u[0], bt.T), supersteps=(16, 24), key_extra="tubes4096-f64")
     out = {"workload": "4096 tubes, L logU[256,8192] (sum 9.26M nodes), D1Q7+D1Q7, one persistent launch",
-           "autotuned_block_superstep": [blk, sup]}
+           "autotuned_block_superstep": [blk, sup], "autotuned_block_superstep_f64": [blk64, sup64]}
     fields = {}
     for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
-        kw = dict(block=blk, superstep=sup) if dt == torch.float32 else {}
+        kw = dict(block=blk, superstep=sup) if dt == torch.float32 else dict(block=blk64, superstep=sup64)
         b = Batch(bt.lengths, bt.n_rot, bt.tau, bt.steps, dtype=dt, **kw).init(bt.rho, bt.u[0], bt.T)
         b.step()  # graph capture outside the timed region
         b.init(bt.rho, bt.u[0], bt.T)
