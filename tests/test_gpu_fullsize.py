@@ -35,11 +35,11 @@ def _window(shape, center, radius):
     return idx.reshape(-1)
 
 
-def _sampled_check(shape, kind, fields, n_rot, tau, steps, gpu, samples, radius):
+def _sampled_check(shape, kind, fields, n_rot, tau, steps, gpu, samples, radius, fd=0.0):
     rho, u, T = fields
     D = len(shape)
     w = 2 * radius + 1
-    G = oracle.Grid(kind, (w,) * D, bc=(oracle.OPEN,) * D, n_rot=n_rot, tau=tau)
+    G = oracle.Grid(kind, (w,) * D, bc=(oracle.OPEN,) * D, n_rot=n_rot, tau=tau, fd_courant=fd)
     centre = (w ** D) // 2
     worst = 0.0
     for c in samples:
@@ -68,6 +68,44 @@ def test_periodic_2d_full_size_sampled(torch_cuda):
     samples = [tuple(int(v) for v in rng.integers(0, 1024, 2)) for _ in range(24)]
     samples += [(0, 0), (1023, 1023), (0, 1023)]
     err = _sampled_check((w.nx, w.ny), oracle.D2Q49, fields, w.n_rot, w.tau, 2, gpu, samples, 8)
+    assert err <= FP32_TOL, err
+
+
+def test_d2q37_full_size_sampled(torch_cuda):
+    """The paper's D2Q37 lattice (Table I) on the same 1024 x 1024 workload,
+    in place as the benchmark runs it (the benchmark's tuned tile gives the
+    same bits as the default one: tile shapes are bitwise identical, tested);
+    moments only, so the lattices' slot orders need not match."""
+    from paper_1606_06107_amd import Sim
+    announce("D2Q37 1024^2 sampled")
+    w = workloads.Periodic2D()
+    fields = w.fields()
+    sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch_cuda.float32, lattice="D2Q37").init(*fields)
+    sim.step(2)
+    gpu = [a.cpu().numpy() for a in sim.moments()[:3]]
+    rng = np.random.default_rng(13)
+    samples = [tuple(int(v) for v in rng.integers(0, 1024, 2)) for _ in range(24)]
+    samples += [(0, 0), (1023, 1023), (0, 1023)]
+    err = _sampled_check((w.nx, w.ny), oracle.D2Q37, fields, w.n_rot, w.tau, 2, gpu, samples, 8)
+    assert err <= FP32_TOL, err
+
+
+def test_fd_2d_full_size_sampled(torch_cuda):
+    """The finite-difference update on the same 1024 x 1024 workload at the
+    benchmark's Courant factor 0.05: after k steps a node depends on the
+    nodes within 2k of it (the upwind stencils reach two nodes per axis)."""
+    from paper_1606_06107_amd import Sim
+    announce("FD 2-D 1024^2 sampled")
+    w = workloads.Periodic2D()
+    fields = w.fields()
+    sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch_cuda.float32).init(*fields)
+    sim.set_fd(0.05)
+    sim.step(3)
+    gpu = [a.cpu().numpy() for a in sim.moments()[:3]]
+    rng = np.random.default_rng(12)
+    samples = [tuple(int(v) for v in rng.integers(0, 1024, 2)) for _ in range(24)]
+    samples += [(0, 0), (1023, 1023), (1023, 0)]
+    err = _sampled_check((w.nx, w.ny), oracle.D2Q49, fields, w.n_rot, w.tau, 3, gpu, samples, 8, fd=0.05)
     assert err <= FP32_TOL, err
 
 
