@@ -72,7 +72,13 @@ class Batch:
         return self
 
     def set_nsteps(self, nsteps):
-        self.nsteps.copy_(torch.as_tensor(np.asarray(nsteps, dtype=np.int64)))
+        """Steps of the next call per tube (copied on the batch's stream, after
+        the work already queued there)."""
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            self.nsteps.copy_(torch.as_tensor(np.asarray(nsteps, dtype=np.int64)))
+        cur.wait_stream(self.stream)
 
     def step(self):
         """Advance every tube i by nsteps[i] steps (one persistent launch)."""

@@ -248,3 +248,37 @@ def test_accepting_everything_chains_the_forward_bitwise(torch_cuda):
     assert acc.cpu().tolist() == [B] * calls
     assert np.array_equal(x.cpu().numpy(), ref.cpu().numpy())
     assert int(fb.steps_done.sum().item()) == 0
+
+
+def test_rollout_on_a_caller_stream(torch_cuda):
+    """The surrogate and its fallback batch on a stream of the caller's (not
+    the current one): the rollout, with fallback steps, equals the one on the
+    current stream bitwise, and a batch on another stream is refused."""
+    announce("rollout on a caller stream")
+    import torch
+    import workloads
+    from paper_1606_06107_amd import Batch, Surrogate
+    from paper_1606_06107_amd.surrogate import rollout
+    B, L, calls = 3, 512, 3
+    bt = workloads.batched_tubes(B, seed=3, fixed_length=L, pr_range=(1.5, 3.0), dr_range=(1.0, 2.0))
+    p = S.init_params(0)
+    x0 = torch.as_tensor(np.stack([bt.rho, bt.u[0], bt.T]).reshape(3, B, L), device="cuda")
+    gamma = torch.as_tensor(bt.gamma, device="cuda")
+    tols = (1e300, -1.0, 1e300)  # reject every step on momentum: all calls fall back
+
+    def run(stream):
+        sur = Surrogate(B, L, stream=stream)
+        sur.set_params(p)
+        fb = Batch(bt.lengths, bt.n_rot, bt.tau, np.zeros(B, dtype=np.int64), dtype=torch.float32, stream=stream)
+        x, acc = rollout(sur, x0, gamma, fb, calls, tols=tols)
+        return x.cpu().numpy(), acc.cpu().numpy(), sur
+
+    ref, acc_ref, sur = run(None)
+    side = torch.cuda.Stream()
+    x, acc, _ = run(side)
+    torch.cuda.synchronize()
+    assert np.array_equal(acc, acc_ref) and int(acc.sum()) == 0
+    assert np.array_equal(x, ref)
+    other = Batch(bt.lengths, bt.n_rot, bt.tau, np.zeros(B, dtype=np.int64), dtype=torch.float32, stream=side)
+    with pytest.raises(ValueError):
+        rollout(sur, x0, gamma, other, 1)
