@@ -118,6 +118,7 @@ class Sim:
                         for a in (rho, u, T)]
         rho_t, u_t, T_t = self._fields
         assert rho_t.numel() == self.N and u_t.numel() == self.D * self.N and T_t.numel() == self.N
+        self.stream.wait_stream(torch.cuda.current_stream(dev))  # conversions above ran there
         self._free()
         h = ctypes.c_void_p()
         with torch.cuda.stream(self.stream):
@@ -131,6 +132,7 @@ class Sim:
         f0 = torch.as_tensor(f0).to(self.device, self.dtype).contiguous()
         g0 = torch.as_tensor(g0).to(self.device, self.dtype).contiguous()
         assert f0.shape == (self.Q, self.N) and g0.shape == (7, self.N)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))  # conversions above ran there
         self._keep = (f0, g0)
         self._free()
         h = ctypes.c_void_p()
