@@ -641,16 +641,18 @@ struct CheckArgs {
     int32_t *accept;
 };
 
-// One workgroup per tube: FP64 totals of x and y in a fixed order.
-__global__ void __launch_bounds__(256) k_check(CheckArgs a) {
-    __shared__ double red[256][7];
+// One workgroup of kChkT threads per tube: FP64 totals of x and y in a
+// fixed order.
+constexpr int kChkT = 1024;
+__global__ void __launch_bounds__(kChkT) k_check(CheckArgs a) {
+    __shared__ double red[kChkT][7];
     __shared__ int bad_s;
     const int b = blockIdx.x;
     const double n = 2.0 / (a.gamma[b] - 1.0) - 1.0;
     const size_t BL = (size_t)a.B * a.L;
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // Mx, Px, Ex, My, Py, Ey, Tmax
     int bad = 0;
-    for (int l = threadIdx.x; l < a.L; l += 256) {
+    for (int l = threadIdx.x; l < a.L; l += kChkT) {
         const size_t i = (size_t)b * a.L + l;
         const double rx = a.x[i], ux = a.x[BL + i], Tx = a.x[2 * BL + i];
         const double ry = a.y[i], uy = a.y[BL + i], Ty = a.y[2 * BL + i];
@@ -669,7 +671,7 @@ __global__ void __launch_bounds__(256) k_check(CheckArgs a) {
     for (int k = 0; k < 7; ++k) red[threadIdx.x][k] = acc[k];
     __syncthreads();
     if (bad) atomicOr(&bad_s, 1);
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kChkT / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
             for (int k = 0; k < 7; ++k)
                 red[threadIdx.x][k] = k == 6 ? fmax(red[threadIdx.x][k], red[threadIdx.x + h][k])
@@ -957,7 +959,7 @@ lbm_status lbm_sur_check(const lbm_sur_desc *d, const double *x, const double *y
     if (st) return st;
     if (!x || !y || !gamma || !accept) return sfail(LBM_EINVAL, "NULL argument");
     CheckArgs a{d->batch, d->length, x, y, gamma, tol_mass, tol_mom, tol_energy, accept};
-    hipLaunchKernelGGL(k_check, dim3(d->batch), dim3(256), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_check, dim3(d->batch), dim3(kChkT), 0, (hipStream_t)stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
 }
