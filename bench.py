@@ -419,8 +419,8 @@ def main():
                          "kernel for scaling HBM traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU "
-              "(see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the benchmark runs on one GPU "
+              "(the multi-GPU sharding of the step is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
