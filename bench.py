@@ -7,7 +7,7 @@ seeded smooth random fields with Mach 0.3, conservation totals reduced in
 FP64 every 100 steps (fused into the step).  One "step" = one time step of
 the whole grid.  Inputs are resident in HBM before timing.
 
-Prints ONE JSON line (rank 0).  --gpus N > 1 is not supported: this build
+Prints ONE JSON line (rank 0).  --gpus N > 1 is not supported: the benchmark
 runs on a single GPU.  Besides the headline workload the line carries
 `extra` measurements of the other workloads (1-D tube, 3-D turbulence,
 batched tubes, learned surrogate vs plain LBM); --no-extras skips them.

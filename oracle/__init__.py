@@ -35,8 +35,8 @@ _DIMOF = {D1Q7: 1, D2Q49: 2, D3Q343: 3, D2Q37: 2}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP).  Building the checker is
-    not using it; the library is only loaded by `lib()`."""
+    """Compile the oracle with gcc (-O2, OpenMP).  Compiling it does not load
+    it; the library is only loaded by `lib()`."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
