@@ -504,7 +504,8 @@ def main():
                                f"FP64 totals every {args.monitor_every} steps",
                    "streaming": "in-place" if sim_inplace else "ping-pong",
                    "nodes": N, "bytes_per_node_step": bytes_per_node,
-                   "tile": list(tuned) if tuned else args.tile or "default"},
+                   "tile": list(tuned) if tuned else ([int(v) for v in args.tile.split("x")] if args.tile
+                                                       else "default")},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
