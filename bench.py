@@ -48,26 +48,72 @@ def kernel_sha():
 METRIC = "MLUPS & % HBM roofline; surrogate vs plain LBM speedup at <=1e-2 L1 error"
 
 
-def cpu_baseline(nx, ny, steps, threads):
-    """The CPU oracle (plain C, FP64) on a bounded sample of the same workload."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(nx, ny, steps, threads, single=(512, 512, 30)):
+    """The CPU oracle (plain C, FP64) on bounded samples of the same workload:
+    all of this process's host cores (at most `threads`), and one core."""
     import numpy as np
 
     import oracle
     import workloads
-    used = oracle.set_threads(threads)
-    w = workloads.Periodic2D(nx=nx, ny=ny)
-    rho, u, T = w.fields()
-    G = oracle.Grid(oracle.D2Q49, (nx, ny), n_rot=w.n_rot, tau=w.tau)
-    f, g = G.init_eq(rho, u, T)
-    G.step(f, g, 1)  # warm-up (page faults, thread start)
-    t0 = time.perf_counter()
-    G.step(f, g, steps)
-    dt = time.perf_counter() - t0
-    assert np.isfinite(f).all()
-    return {"value": round(nx * ny * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": used,
-            "kind": "oracle",
+
+    def run(nx_, ny_, steps_, th):
+        used = oracle.set_threads(th)
+        w = workloads.Periodic2D(nx=nx_, ny=ny_)
+        rho, u, T = w.fields()
+        G = oracle.Grid(oracle.D2Q49, (nx_, ny_), n_rot=w.n_rot, tau=w.tau)
+        f, g = G.init_eq(rho, u, T)
+        G.step(f, g, 1)  # warm-up (page faults, thread start)
+        t0 = time.perf_counter()
+        G.step(f, g, steps_)
+        dt = time.perf_counter() - t0
+        assert np.isfinite(f).all()
+        return used, nx_ * ny_ * steps_ / dt / 1e6, dt
+
+    used, mlups, dt = run(nx, ny, steps, threads)
+    s_nx, s_ny, s_steps = single
+    _, mlups1, dt1 = run(s_nx, s_ny, s_steps, 1)
+    oracle.set_threads(threads)
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"{nx}x{ny} nodes x {steps} steps of the same 2-D workload, FP64, "
-                      f"{dt:.1f} s wall"}
+                      f"{used} threads, {dt:.1f} s wall",
+            "single_core": {"value": round(mlups1, 4), "unit": "MLUPS",
+                            "sample": f"{s_nx}x{s_ny} nodes x {s_steps} steps, 1 thread, {dt1:.1f} s wall"},
+            "cpu_model": _cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
+
+
+def copy_bandwidth(mbytes, reps=10):
+    """Device-to-device copy of `mbytes` MB (torch's copy kernel), GB/s
+    counting the bytes read plus the bytes written; median of `reps`."""
+    import torch
+    n = int(mbytes * 1e6) // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    ms = ts[len(ts) // 2]
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
 
 
 def _events(stream):
@@ -84,8 +130,8 @@ def extra_tube_1d():
     from paper_1606_06107_amd import Sim
     w = workloads.tube_1d()
     sim = Sim((w.N,), bc=["open"], n_rot=w.n_rot, tau=w.tau, dtype=torch.float64).init(*w.fields())
-    sim.step(w.steps)  # capture + warm
-    sim.init(*w.fields())
+    sim.step(w.steps)  # warm
+    sim.init(*w.fields()).prepare(w.steps)  # a new handle: record its graph before timing
     a, b = _events(sim.stream)
     torch.cuda.synchronize()
     a.record(sim.stream)
@@ -132,6 +178,7 @@ def extra_3d(steps=10):
         sim = Sim((w.n,) * 3, n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields())
         sim.set_blocked(blocked)
         sim.step(2)
+        sim.prepare(steps)
         a, b = _events(sim.stream)
         torch.cuda.synchronize()
         a.record(sim.stream)
@@ -165,9 +212,10 @@ def extra_d2q37(steps=200):
     from paper_1606_06107_amd.autotune import tune_sim
     w = workloads.Periodic2D()
     sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32, lattice="D2Q37").init(*w.fields())
-    tile, _ = tune_sim(sim, steps=20, reps=2)
+    tile, _ = tune_sim(sim, steps=20)
     sim.init(*w.fields())
-    sim.step(steps)  # capture + warm
+    sim.step(steps)  # warm
+    sim.prepare(steps)
     a, b = _events(sim.stream)
     torch.cuda.synchronize()
     a.record(sim.stream)
@@ -187,8 +235,8 @@ def extra_d2q37(steps=200):
     rho = np.tile(np.where(x < 0.5, 4.0, 1.0), ny)
     tube = Sim((Nx, ny), bc=["open", "periodic"], n_rot=3.0, tau=2.0 / 3.0, dtype=torch.float64,
                lattice="D2Q37")
-    tube.init(rho, np.zeros((2, Nx * ny)), np.ones(Nx * ny)).step(st)  # capture + warm
-    tube.init(rho, np.zeros((2, Nx * ny)), np.ones(Nx * ny))
+    tube.init(rho, np.zeros((2, Nx * ny)), np.ones(Nx * ny)).step(st)  # warm
+    tube.init(rho, np.zeros((2, Nx * ny)), np.ones(Nx * ny)).prepare(st)
     a, b = _events(tube.stream)
     torch.cuda.synchronize()
     a.record(tube.stream)
@@ -215,8 +263,8 @@ def extra_fd(steps=200, courant=0.05):
     from paper_1606_06107_amd import Sim
     w = workloads.Periodic2D()
     sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields()).set_fd(courant)
-    sim.step(steps)  # capture + warm
-    sim.init(*w.fields())
+    sim.step(steps)  # warm
+    sim.init(*w.fields()).prepare(steps)
     a, b = _events(sim.stream)
     torch.cuda.synchronize()
     a.record(sim.stream)
@@ -395,6 +443,74 @@ def extra_surrogate(train_candidates=8192, test_candidates=2048, train_steps=300
             "one_call_rel_l1_identity": [round(float(v), 5) for v in err_one_id]}
 
 
+def extra_hbm(steps=40, warmup=10, sizes=((1024, 1024), (4096, 2048))):
+    """The headline step at two sizes, in place and ping-pong: 1024^2 (in
+    place its 264 MB working set about fits the 256 MB memory-side cache) and
+    4096 x 2048 (2.1 GB in place, 3.8 GB ping-pong: 8x / 15x that cache, so
+    the memory traffic is HBM traffic).  Autotuned tile per case."""
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    from paper_1606_06107_amd.autotune import tune_sim
+    rows = []
+    for nx, ny in sizes:
+        w = workloads.Periodic2D(nx=nx, ny=ny)
+        fields = w.fields()
+        for inplace in (True, False):
+            sim = Sim((nx, ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*fields)
+            sim.set_inplace(inplace)
+            tile, _ = tune_sim(sim, steps=10, reps=3, finalists=2)
+            sim.init(*fields)
+            sim.step(warmup)
+            sim.prepare(steps)
+            a, b = _events(sim.stream)
+            torch.cuda.synchronize()
+            a.record(sim.stream)
+            sim.step(steps)
+            b.record(sim.stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            N = nx * ny
+            gbs = N * 448 / (ms * 1e-3) / 1e9
+            ok = bool(torch.isfinite(sim.moments(totals=False)[2]).all().item())
+            ws = N * (49 * (1 if inplace else 2) + 14) * 4
+            rows.append({"nodes": f"{nx}x{ny}", "streaming": "in-place" if inplace else "ping-pong",
+                         "working_set_MB": round(ws / 1e6, 1), "tile": list(tile[:2]),
+                         "ms_per_step": round(ms, 4), "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1),
+                         "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok})
+            del sim
+            torch.cuda.empty_cache()
+    return {"workload": "headline 2-D step (D2Q49+D1Q7 FP32, 448 B per node-step) at a cache-sized and "
+                        "an HBM-sized grid", "rows": rows}
+
+
+def tile_sweep(nx, ny, steps, inplace):
+    """Every compiled 2-D tile for `steps` steps (a profiling aid: under
+    rocprofv3 each tile's kernel gets its own statistics line)."""
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    from paper_1606_06107_amd.autotune import TILES
+    w = workloads.Periodic2D(nx=nx, ny=ny)
+    sim = Sim((nx, ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields())
+    sim.set_inplace(inplace)
+    out = {}
+    for t in TILES[2]:
+        sim.set_tile(*t)
+        sim.prepare(steps)
+        a, b = _events(sim.stream)
+        torch.cuda.synchronize()
+        a.record(sim.stream)
+        sim.step(steps)
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        out["x".join(map(str, t))] = round(1000 * a.elapsed_time(b) / steps, 2)
+    print(json.dumps({"tile_sweep_us_per_step": out, "nodes": f"{nx}x{ny}",
+                      "streaming": "in-place" if inplace else "ping-pong"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,7 +523,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", type=str, default="tube_1d,turbulence_3d,d2q37,fd,transport,batched_tubes,surrogate",
+    ap.add_argument("--extras", type=str,
+                    default="hbm,tube_1d,turbulence_3d,d2q37,fd,transport,batched_tubes,surrogate",
                     help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--sur-train-steps", type=int, default=30000,
@@ -417,6 +534,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first run a plain device copy of this many MB (5 times): the reference "
                          "kernel for scaling HBM traffic counters")
+    ap.add_argument("--tile-sweep", action="store_true",
+                    help="only run every compiled 2-D tile for --steps steps (for profiling) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: the benchmark runs on one GPU "
@@ -438,23 +557,27 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.tile_sweep:
+        tile_sweep(args.nx, args.ny, args.steps, not args.ping_pong)
+        return
     w = workloads.Periodic2D(nx=args.nx, ny=args.ny)
     rho, u, T = w.fields()
     N = args.nx * args.ny
     sim = Sim((args.nx, args.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(rho, u, T)
     sim_inplace = not args.ping_pong
     sim.set_inplace(sim_inplace)
-    tuned = None
+    tuned, tune_table = None, None
     if args.tile:
         sim.set_tile(*[int(v) for v in args.tile.split("x")])
     elif not args.no_autotune:
         from paper_1606_06107_amd.autotune import tune_sim
-        tuned, _ = tune_sim(sim, steps=20, reps=2)
+        tuned, tune_table = tune_sim(sim, steps=20)
         sim.init(rho, u, T)  # tuning advanced the state; start over
     total_steps = args.warmup + args.steps
     cap = total_steps // args.monitor_every + 2
     series = sim.set_monitor(args.monitor_every, cap)
     sim.step(args.warmup)
+    sim.prepare(args.steps)  # the timed call's graph is recorded before timing
     stream = sim.stream
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -485,6 +608,9 @@ def main():
     mlups = N / (ms_per_step * 1e-3) / 1e6
     bytes_per_node = 2 * (49 + 7) * 4  # read + write every population once
     achieved_gbs = N * bytes_per_node / (ms_per_step * 1e-3) / 1e9
+    del sim
+    torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth(1024)  # 1 GB: well beyond the memory-side cache
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -504,20 +630,21 @@ def main():
                                f"FP64 totals every {args.monitor_every} steps",
                    "streaming": "in-place" if sim_inplace else "ping-pong",
                    "nodes": N, "bytes_per_node_step": bytes_per_node,
-                   "tile": list(tuned) if tuned else ([int(v) for v in args.tile.split("x")] if args.tile
-                                                       else "default")},
+                   "tile": list(used_tile)},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic, "copy_GBps": copy_gbs,
+                     "frac_of_copy": round(achieved_gbs / copy_gbs, 4)},
         "checks": {"finite": finite, "mass_drift": mass_drift, "momentum_drift": mom_drift,
                    "energy_drift_n3": energy_drift, "wall_s": round(wall, 3)},
     }
-    del sim
+    if tune_table is not None:
+        out["autotune"] = tune_table
     if not args.no_extras:
         extra = {}
         wanted = set(args.extras.split(","))
-        for name, fn in (("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d), ("d2q37", extra_d2q37),
-                         ("fd", extra_fd),
+        for name, fn in (("hbm", extra_hbm), ("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d),
+                         ("d2q37", extra_d2q37), ("fd", extra_fd),
                          ("transport", extra_transport), ("batched_tubes", extra_batch),
                          ("surrogate", lambda: extra_surrogate(train_steps=args.sur_train_steps))):
             if name not in wanted:
@@ -528,6 +655,7 @@ def main():
         out["extra"] = extra
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
+        print("bench: cpu_baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.nx, args.ny, args.cpu_steps, threads)
     print(json.dumps(out), flush=True)
 

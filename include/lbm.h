@@ -115,6 +115,18 @@ lbm_status lbm_init_populations(const lbm_desc *desc, const void *f0, const void
  * Errors: LBM_EINVAL, LBM_ELAUNCH. */
 lbm_status lbm_step(lbm_sim sim, int64_t nsteps);
 
+/* Record and instantiate, without running it, the HIP graph that
+ * lbm_step(sim, nsteps) replays from the current state, so that the later
+ * lbm_step call only launches it (capture and instantiation take host time,
+ * and allocate; callers that time or serve steps do them ahead).  A graph
+ * is reused by any lbm_step of the same length that starts from a state with
+ * the same buffer parity, streaming layout, tile and monitor settings and
+ * the same phase t mod every of the monitor (the row a monitored step fills
+ * comes from a counter in the workspace, not from the recorded time).  Up
+ * to 8 graphs are kept per handle.  No-op when graphs are disabled or
+ * nsteps <= 1.  Errors: LBM_EINVAL, LBM_EUNSUPPORTED, LBM_ELAUNCH. */
+lbm_status lbm_prepare(lbm_sim sim, int64_t nsteps);
+
 /* Fields and conservation totals at the current time.  rho[N], u[D][N], T[N]
  * and totals[2+D] = {mass, momentum_0..D-1, energy} (energy = sum over nodes
  * of E_t + rho e_r, i.e. rho (|u|^2/2 + (D+n)T/2)), all device FP64; any may
@@ -131,7 +143,10 @@ lbm_status lbm_populations(lbm_sim sim, void *f_out, void *g_out);
 /* Record conservation totals every `every` steps during lbm_step, fused into
  * the step kernel: row k of series[capacity][2+D] (device FP64) receives the
  * totals of time t with t = k*every (t counted from lbm_init).  Steps whose
- * row is >= capacity record nothing.  every = 0 switches recording off. */
+ * row is >= capacity record nothing.  every = 0 switches recording off.
+ * The next row to fill is kept in the workspace (set here, on the sim's
+ * stream), so the workspace must not be shared by two handles that record
+ * at the same time. */
 lbm_status lbm_set_monitor(lbm_sim sim, int64_t every, double *series, int64_t capacity);
 
 /* Time-step counter since lbm_init. */
@@ -253,6 +268,13 @@ lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const d
  * longest work first.  The result is left in f[0], g[0]; status[i] is
  * written by the end of the launch. */
 lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream);
+
+/* Release the HIP graph lbm_batch_step keeps for this descriptor on the
+ * current device (the library records one per distinct descriptor and device,
+ * at most 16, and otherwise keeps them until the process ends).  Call it
+ * before freeing the descriptor's buffers.  A later lbm_batch_step with the
+ * same descriptor records a new graph.  Errors: LBM_EINVAL, LBM_EDEVICE. */
+lbm_status lbm_batch_release(const lbm_batch_desc *desc);
 
 /* Packed FP64 fields rho[total], u[total], T[total] of the state in f[0], g[0];
  * any may be NULL. */

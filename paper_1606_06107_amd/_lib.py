@@ -48,6 +48,7 @@ SIGNATURES = {
     "lbm_init": (c_i32, [ctypes.POINTER(LbmDesc), c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_vp)]),
     "lbm_init_populations": (c_i32, [ctypes.POINTER(LbmDesc), c_vp, c_vp, c_vp, ctypes.POINTER(c_vp)]),
     "lbm_step": (c_i32, [c_vp, c_i64]),
+    "lbm_prepare": (c_i32, [c_vp, c_i64]),
     "lbm_moments": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbm_populations": (c_i32, [c_vp, c_vp, c_vp]),
     "lbm_set_monitor": (c_i32, [c_vp, c_i64, c_vp, c_i64]),
@@ -63,6 +64,7 @@ SIGNATURES = {
     "lbm_batch_workspace_bytes": (c_sz, [ctypes.POINTER(LbmBatchDesc)]),
     "lbm_batch_init": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp, c_vp, c_vp, c_vp]),
     "lbm_batch_step": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp]),
+    "lbm_batch_release": (c_i32, [ctypes.POINTER(LbmBatchDesc)]),
     "lbm_batch_moments": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp, c_vp, c_vp, c_vp]),
     "lbm_sur_bf16_bytes": (c_sz, []),
     "lbm_sur_workspace_bytes": (c_sz, [ctypes.POINTER(LbmSurDesc)]),

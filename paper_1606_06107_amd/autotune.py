@@ -46,21 +46,32 @@ def _store():
             json.dump(_mem, fh, indent=1, sort_keys=True)
 
 
-def _time(fn, reps, stream):
-    fn()  # warm-up (graph capture, caches)
+def _time_calls(fn, reps, stream):
+    """Median over `reps` calls of fn() (ms), each bracketed by its own
+    events; the first call (graph recording, caches) is not timed."""
+    fn()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
+    ts = []
     for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
         fn()
-    b.record(stream)
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
 
 
-def tune_sim(sim, steps=20, reps=3, force=False):
-    """Pick the fastest tile of the per-step kernel for this Sim (advances it
-    by (len(tiles) * (reps + 1)) * steps steps).  Returns (tile, table)."""
+def tune_sim(sim, steps=20, reps=5, finalists=3, force=False):
+    """Pick the fastest tile of the per-step kernel for this Sim.
+
+    Round 1 times every compiled tile (median of `reps` calls of
+    step(steps)); round 2 times the `finalists` fastest again, interleaved
+    call by call so that drift of the clock or the memory affects them
+    alike, and picks the smallest median.  Advances the Sim.  Returns
+    (tile, table) with table = {"round1": {tile: ms per step},
+    "round2": {...}}."""
     _load()
     key = (f"step|D{sim.D}|lat{sim.lattice}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|ip{sim._inplace}"
            f"|blk{sim._blocked}|{_arch()}")
@@ -68,7 +79,7 @@ def tune_sim(sim, steps=20, reps=3, force=False):
         t = tuple(_mem[key]["best"])
         sim.set_tile(*t)
         return t, _mem[key]["table"]
-    table = {}
+    r1 = {}
     for t in TILES[sim.D]:
         try:
             sim.set_tile(*t)
@@ -76,10 +87,28 @@ def tune_sim(sim, steps=20, reps=3, force=False):
             if e.status != LBM_EUNSUPPORTED:
                 raise
             continue
-        table["x".join(map(str, t))] = _time(lambda: sim.step(steps), reps, sim.stream) / steps
-    best = min(table, key=table.get)
+        r1["x".join(map(str, t))] = _time_calls(lambda: sim.step(steps), reps, sim.stream) / steps
+    fin = sorted(r1, key=r1.get)[:max(1, finalists)]
+    runs = {k: [] for k in fin}
+    for k in fin:  # record every finalist's graph before timing any
+        sim.set_tile(*[int(v) for v in k.split("x")])
+        sim.prepare(steps)
+    for _ in range(reps):
+        for k in fin:
+            sim.set_tile(*[int(v) for v in k.split("x")])
+            sim.prepare(steps)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(sim.stream)
+            sim.step(steps)
+            b.record(sim.stream)
+            torch.cuda.synchronize()
+            runs[k].append(a.elapsed_time(b) / steps)
+    r2 = {k: sorted(v)[len(v) // 2] for k, v in runs.items()}
+    best = min(r2, key=r2.get)
     bt = tuple(int(v) for v in best.split("x"))
     sim.set_tile(*bt)
+    table = {"round1": {k: round(v, 5) for k, v in r1.items()}, "round2": {k: round(v, 5) for k, v in r2.items()}}
     _mem[key] = {"best": list(bt), "table": table}
     _store()
     return bt, table

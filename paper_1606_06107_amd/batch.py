@@ -94,6 +94,18 @@ class Batch:
         L.check(self.lib.lbm_batch_moments(ctypes.byref(self.desc), _p(r), _p(u), _p(T), self._s()))
         return r, u, T
 
+    def release(self):
+        """Drop the library's HIP graph for this batch (its buffers are about
+        to be freed); a later step() records a new one."""
+        if getattr(self, "desc", None) is not None:
+            L.check(self.lib.lbm_batch_release(ctypes.byref(self.desc)))
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
     def split(self, packed):
         """Host list of per-tube arrays from a packed device or host array."""
         a = packed.cpu().numpy() if torch.is_tensor(packed) else np.asarray(packed)

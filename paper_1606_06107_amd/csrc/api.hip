@@ -81,6 +81,13 @@ int64_t max_partial_rows(const lbm_desc *d) {
     return rows;
 }
 
+// Byte offset of the conservation monitor's row counter (one int64) in the
+// workspace, after the partial rows.
+size_t monitor_slot_offset(const lbm_desc *d) {
+    const size_t rows = (size_t)max_partial_rows(d);
+    return ((rows * (2 + d->dim) * sizeof(double) + 255) / 256) * 256;
+}
+
 lbm_status validate(const lbm_desc *d) {
     if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
     if (d->abi_version != LBM_ABI_VERSION)
@@ -137,7 +144,7 @@ struct lbm_sim_s {
     double *mon_series = nullptr;
     int64_t mon_cap = 0;
     struct Entry {
-        int64_t n, t0, every;
+        int64_t n, t0, every, cap;
         int fcur, gcur, layout, inplace, tile0, tile1;
         double *series;
         hipGraphExec_t exec;
@@ -153,6 +160,10 @@ void clear_cache(lbm_sim s) {
 }
 
 int64_t N_of(const lbm_desc &d) { return d.n[0] * d.n[1] * d.n[2]; }
+
+int64_t *monitor_slot(lbm_sim s) {
+    return reinterpret_cast<int64_t *>(static_cast<char *>(s->d.workspace) + monitor_slot_offset(&s->d));
+}
 
 // Host-side state after n more steps (the time counter aside).
 void advance(lbm_sim s, int64_t n) {
@@ -222,15 +233,16 @@ hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
     a.omega = 1.0 / d.tau;
     a.n_rot = d.n_rot;
     a.ntiles = lbmx::step_ntiles(d.dim, s->tile, a.n0, a.n1, a.n2, &a.tiles0, &a.tiles1, &a.tiles2);
-    const bool mon = s->mon_every > 0 && s->t % s->mon_every == 0 &&
-                     s->t / s->mon_every < s->mon_cap;
+    // Monitored steps depend on t mod every only; the row they fill comes
+    // from the device-side counter (set by lbm_set_monitor), so a recorded
+    // graph of steps replays correctly from any start with the same phase.
+    const bool mon = s->mon_every > 0 && s->t % s->mon_every == 0;
     a.partials = mon ? (double *)d.workspace : nullptr;
     hipError_t e = lbmx::launch_step(d.dtype, d.dim, kind_of(d.lattice), s->tile, a, st);
     if (e != hipSuccess) return e;
     if (mon) {
-        const int K = 2 + d.dim;
-        e = lbmx::launch_reduce((const double *)d.workspace, a.ntiles, K,
-                                s->mon_series + (s->t / s->mon_every) * K, st);
+        e = lbmx::launch_reduce_series((const double *)d.workspace, a.ntiles, 2 + d.dim, s->mon_series,
+                                       s->mon_cap, monitor_slot(s), st);
         if (e != hipSuccess) return e;
     }
     advance(s, 1);
@@ -291,6 +303,51 @@ lbm_status make_sim(const lbm_desc *desc, void *stream, lbm_sim *out) {
     return LBM_OK;
 }
 
+// The instantiated graph of nsteps launches from the current state: from the
+// cache, or recorded on the private stream and instantiated (and cached).
+// The key holds everything the recorded launches depend on: buffer indices,
+// layout, scheme, tile, monitor settings and the phase t mod every.
+lbm_status graph_for(lbm_sim s, int64_t nsteps, hipGraphExec_t *out) {
+    const bool mon = s->mon_every > 0;
+    const int64_t t0key = mon ? s->t % s->mon_every : -1;
+    for (auto &en : s->cache) {
+        if (en.n == nsteps && en.fcur == s->fcur && en.gcur == s->gcur && en.layout == s->layout &&
+            en.inplace == s->inplace && en.t0 == t0key && en.tile0 == s->tile[0] &&
+            en.tile1 == s->tile[1] && en.every == s->mon_every && en.cap == s->mon_cap &&
+            en.series == s->mon_series) {
+            *out = en.exec;
+            return LBM_OK;
+        }
+    }
+    const int fcur0 = s->fcur, gcur0 = s->gcur, lay0 = s->layout;
+    const int64_t t0 = s->t;
+    hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue_step(s, s->capture);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->capture, &graph);
+    s->fcur = fcur0;  // recording only: the host-side state stays where it was
+    s->gcur = gcur0;
+    s->layout = lay0;
+    s->t = t0;
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    if (s->cache.size() >= 8) {
+        hipGraphExecDestroy(s->cache.front().exec);
+        s->cache.erase(s->cache.begin());
+    }
+    s->cache.push_back({nsteps, t0key, s->mon_every, s->mon_cap, fcur0, gcur0, lay0, s->inplace,
+                        s->tile[0], s->tile[1], s->mon_series, exec});
+    *out = exec;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -299,8 +356,7 @@ size_t lbm_workspace_bytes(const lbm_desc *desc) {
     if (!desc || desc->dim < 1 || desc->dim > 3) return 0;
     for (int a = 0; a < 3; ++a)
         if (desc->n[a] < 1) return 0;
-    const size_t rows = (size_t)max_partial_rows(desc);
-    return ((rows * (2 + desc->dim) * sizeof(double) + 255) / 256) * 256;
+    return monitor_slot_offset(desc) + 256;
 }
 
 lbm_status lbm_init(const lbm_desc *desc, const double *rho, const double *u, const double *T,
@@ -358,51 +414,24 @@ lbm_status lbm_step(lbm_sim s, int64_t nsteps) {
         }
         return LBM_OK;
     }
-    const bool mon = s->mon_every > 0;
-    const int64_t t0key = mon ? s->t : -1;
-    for (auto &en : s->cache) {
-        if (en.n == nsteps && en.fcur == s->fcur && en.gcur == s->gcur && en.layout == s->layout &&
-            en.inplace == s->inplace && en.t0 == t0key &&
-            en.tile0 == s->tile[0] && en.tile1 == s->tile[1] && en.every == s->mon_every &&
-            en.series == s->mon_series) {
-            hipError_t e = hipGraphLaunch(en.exec, s->stream);
-            if (e != hipSuccess) return hip_fail(e, "graph launch");
-            advance(s, nsteps);
-            s->t += nsteps;
-            return LBM_OK;
-        }
-    }
-    // Record nsteps launches on the private stream and replay them as one graph.
-    const int fcur0 = s->fcur, gcur0 = s->gcur, lay0 = s->layout;
-    const int64_t t0 = s->t;
-    hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "begin capture");
-    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue_step(s, s->capture);
-    hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s->capture, &graph);
-    s->fcur = fcur0;
-    s->gcur = gcur0;
-    s->layout = lay0;
-    s->t = t0;
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
-        return hip_fail(e != hipSuccess ? e : e2, "graph capture");
-    }
     hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-    if (s->cache.size() >= 8) {
-        hipGraphExecDestroy(s->cache.front().exec);
-        s->cache.erase(s->cache.begin());
-    }
-    s->cache.push_back({nsteps, t0key, s->mon_every, fcur0, gcur0, lay0, s->inplace, s->tile[0],
-                        s->tile[1], s->mon_series, exec});
-    e = hipGraphLaunch(exec, s->stream);
+    lbm_status st = graph_for(s, nsteps, &exec);
+    if (st) return st;
+    hipError_t e = hipGraphLaunch(exec, s->stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     advance(s, nsteps);
-    s->t = t0 + nsteps;
+    s->t += nsteps;
     return LBM_OK;
+}
+
+lbm_status lbm_prepare(lbm_sim s, int64_t nsteps) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (!s->graphs || nsteps <= 1) return LBM_OK;
+    if (s->fd > 0.0 && s->mon_every > 0)
+        return fail(LBM_EUNSUPPORTED, "the conservation monitor is not available with the finite-difference update");
+    hipGraphExec_t exec = nullptr;
+    return graph_for(s, nsteps, &exec);
 }
 
 lbm_status lbm_moments(lbm_sim s, double *rho, double *u, double *T, double *totals) {
@@ -445,6 +474,10 @@ lbm_status lbm_set_monitor(lbm_sim s, int64_t every, double *series, int64_t cap
     if (every < 0 || capacity < 0) return fail(LBM_EINVAL, "every and capacity must be >= 0");
     if (every > 0 && (!series || capacity == 0))
         return fail(LBM_EINVAL, "series buffer and capacity required when every > 0");
+    if (every > 0) {  // the next recorded time t = k * every >= now fills row k
+        const hipError_t e = lbmx::launch_set_i64(monitor_slot(s), (s->t + every - 1) / every, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "monitor counter");
+    }
     s->mon_every = every;
     s->mon_series = every > 0 ? series : nullptr;
     s->mon_cap = every > 0 ? capacity : 0;

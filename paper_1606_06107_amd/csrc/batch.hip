@@ -804,10 +804,15 @@ template <typename P> hipError_t launch_batch_p(const Launch &L, const lbmx::Bat
     return hipErrorInvalidValue;
 }
 
+// Instantiated graphs of lbm_batch_step, keyed by the device and every
+// descriptor field the recorded launches read; released by
+// lbm_batch_release (or evicted oldest-first beyond kGraphCap entries).
 struct GraphEntry {
+    int dev;
     lbm_batch_desc d;
     hipGraphExec_t exec;
 };
+constexpr size_t kGraphCap = 16;
 std::mutex g_mu;
 std::vector<GraphEntry> g_cache;
 
@@ -895,9 +900,11 @@ lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream) {
     st = plan(desc, &L);
     if (st) return st;
     hipStream_t s = (hipStream_t)hip_stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return bfail(LBM_EDEVICE, "hipGetDevice failed");
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &en : g_cache)
-        if (same_desc(en.d, *desc)) {
+        if (en.dev == dev && same_desc(en.d, *desc)) {
             hipError_t e = hipGraphLaunch(en.exec, s);
             if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
             return LBM_OK;
@@ -922,13 +929,29 @@ lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream) {
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph instantiate: ") + hipGetErrorString(e));
-    if (g_cache.size() >= 16) {
+    if (g_cache.size() >= kGraphCap) {
         hipGraphExecDestroy(g_cache.front().exec);
         g_cache.erase(g_cache.begin());
     }
-    g_cache.push_back({*desc, exec});
+    g_cache.push_back({dev, *desc, exec});
     e = hipGraphLaunch(exec, s);
     if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_release(const lbm_batch_desc *desc) {
+    if (!desc) return bfail(LBM_EINVAL, "batch descriptor is NULL");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return bfail(LBM_EDEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (size_t k = 0; k < g_cache.size();) {
+        if (g_cache[k].dev == dev && same_desc(g_cache[k].d, *desc)) {
+            hipGraphExecDestroy(g_cache[k].exec);
+            g_cache.erase(g_cache.begin() + (ptrdiff_t)k);
+        } else {
+            ++k;
+        }
+    }
     return LBM_OK;
 }
 

@@ -154,9 +154,16 @@ __global__ void __launch_bounds__(256) k_to_blocked(int Q, uint32_t N, const P *
     dst[e] = src[(size_t)i * N + x];
 }
 
+// Fixed-order sum of partials[nparts][K] (K <= 8).  series == NULL: the sums
+// go to out[K].  Otherwise they are a row of the conservation series: row
+// *slot of series[cap][K] receives them if *slot < cap, and *slot advances by
+// one either way (the row counter lives in device memory, so a recorded
+// sequence of steps does not depend on the absolute time it started at).
 __global__ void __launch_bounds__(256) k_reduce(const double *partials, int nparts, int K,
-                                                double *out) {
+                                                double *out, double *series, int64_t cap,
+                                                int64_t *slot) {
     __shared__ double s[256];
+    __shared__ double res[8];
     for (int k = 0; k < K; ++k) {
         double acc = 0.0;
         for (int p = threadIdx.x; p < nparts; p += 256) acc += partials[(size_t)p * K + k];
@@ -166,9 +173,23 @@ __global__ void __launch_bounds__(256) k_reduce(const double *partials, int npar
             if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) out[k] = s[0];
+        if (threadIdx.x == 0) res[k] = s[0];
         __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        double *dst = out;
+        if (series) {
+            const int64_t row = *slot;
+            dst = row >= 0 && row < cap ? series + row * K : nullptr;
+            *slot = row + 1;
+        }
+        if (dst)
+            for (int k = 0; k < K; ++k) dst[k] = res[k];
+    }
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -257,7 +278,22 @@ hipError_t launch_export(int dtype, int dim, int kind, const FieldArgs &a, hipSt
 }
 
 hipError_t launch_reduce(const double *partials, int nparts, int K, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, K, out);
+    if (K < 1 || K > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, K, out, (double *)nullptr,
+                       (int64_t)0, (int64_t *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_series(const double *partials, int nparts, int K, double *series, int64_t cap,
+                                int64_t *slot, hipStream_t s) {
+    if (K < 1 || K > 8 || !series || !slot) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, K, (double *)nullptr, series,
+                       cap, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();
 }
 

@@ -104,5 +104,11 @@ hipError_t launch_fields(int dtype, int dim, int kind, const FieldArgs &a, int *
 hipError_t launch_export(int dtype, int dim, int kind, const FieldArgs &a, hipStream_t s);
 // Fixed-order sum of partials[nparts][K] into out[K] (one workgroup).
 hipError_t launch_reduce(const double *partials, int nparts, int K, double *out, hipStream_t s);
+// The same sum as row *slot of series[cap][K] (skipped if *slot >= cap);
+// *slot then advances by one (device int64).
+hipError_t launch_reduce_series(const double *partials, int nparts, int K, double *series, int64_t cap,
+                                int64_t *slot, hipStream_t s);
+// *p = v on the stream (a kernel, so the write may be part of a graph).
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);
 
 }  // namespace lbmx

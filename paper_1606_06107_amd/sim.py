@@ -146,6 +146,13 @@ class Sim:
         L.check(self.lib.lbm_step(self.handle, int(nsteps)))
         return self
 
+    def prepare(self, nsteps):
+        """Record and instantiate the HIP graph of step(nsteps) from the
+        current state without running it (host work done ahead of a timed
+        or latency-critical call)."""
+        L.check(self.lib.lbm_prepare(self.handle, int(nsteps)))
+        return self
+
     def set_graphs(self, on: bool):
         L.check(self.lib.lbm_set_graphs(self.handle, 1 if on else 0))
         self._graphs = bool(on)

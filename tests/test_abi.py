@@ -157,3 +157,9 @@ def test_surrogate_parameter_layout_matches_reference(lib):
     from oracle import surrogate_ref as S
     from paper_1606_06107_amd import surrogate
     assert S.NPARAMS == lib.LBM_SUR_NPARAMS == surrogate.NPARAMS
+
+
+def test_batch_release_rejects_null(lib):
+    L = lib.load()
+    assert L.lbm_batch_release(None) == lib.LBM_EINVAL
+    assert L.lbm_prepare(None, 5) == lib.LBM_EINVAL

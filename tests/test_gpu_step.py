@@ -267,6 +267,37 @@ def test_monitor_series_matches_moments(torch_cuda):
     assert abs(tot[0] - s[0, 0]) < 2e-8 * s[0, 0]
 
 
+def test_monitored_graphs_replay_by_phase(torch_cuda):
+    """A monitored multi-step graph is keyed by the phase t mod every: calls
+    of 25 steps with every = 10 start at phases 0, 5, 0, 5, so the third and
+    fourth replay the graphs recorded by the first two, at a later time.  The
+    series (rows from the device-side counter) and the state must equal
+    those of launches without graphs, bitwise; rows past the capacity are
+    dropped.  prepare() records a graph without running it."""
+    import torch
+    from paper_1606_06107_amd import Sim
+    shape = (64, 40)
+    fields = smooth_fields(shape, 9)
+    announce("monitor graphs keyed by phase")
+    out = []
+    for graphs in (True, False):
+        sim = Sim(shape, n_rot=3.0, tau=0.9, dtype=torch.float32).init(*fields)
+        sim.set_graphs(graphs)
+        series = sim.set_monitor(every=10, capacity=9)
+        if graphs:
+            sim.prepare(25)
+            assert sim.t == 0
+        for _ in range(4):
+            sim.step(25)
+        assert sim.t == 100
+        f, g = sim.populations()
+        torch.cuda.synchronize()
+        out.append((series.cpu().numpy(), f.cpu().numpy(), g.cpu().numpy()))
+    (sa, fa, ga), (sb, fb, gb) = out
+    assert np.isfinite(sa).all() and np.array_equal(sa, sb)  # rows t = 0, 10, ..., 80
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
 def test_fp64_conservation_periodic_2d(torch_cuda):
     shape = (80, 64)
     fields = smooth_fields(shape, 3)
