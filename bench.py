@@ -49,14 +49,21 @@ METRIC = "MLUPS & % HBM roofline; surrogate vs plain LBM speedup at <=1e-2 L1 er
 
 
 def _cpu_model():
+    """Model name of the host CPU, with its family/model numbers (a virtual
+    machine may report only a generic name)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k in ("model name", "cpu family", "model") and k not in info:
+                    info[k] = v.strip()
+                if len(info) == 3:
+                    break
     except OSError:
         pass
-    return "unknown"
+    return f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, model {info.get('model', '?')})"
 
 
 def cpu_baseline(nx, ny, steps, threads, single=(512, 512, 30)):

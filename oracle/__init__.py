@@ -40,12 +40,12 @@ def build(force: bool = True) -> str:
 
     ISO C mode (-std=c99) keeps multiply-adds unfused (-ffp-contract=off), so
     the arithmetic is the one written, whatever the instruction set.  The
-    instruction set is x86-64-v3 (AVX2, FMA) rather than the build host's
-    own: the library is compiled on one machine and may run on another host
-    CPU."""
+    instruction set is x86-64-v4 (AVX-512) rather than the build host's own
+    (-march=native): the library is compiled on one machine and runs on
+    another host CPU as well."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-std=c99", "-ffp-contract=off",
+        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v4", "-std=c99", "-ffp-contract=off",
                                "-fPIC", "-shared", "-fopenmp", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

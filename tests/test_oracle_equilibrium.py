@@ -81,10 +81,25 @@ def test_equilibria_at_rest_are_weights(orc):
     assert np.allclose(orc.geq(1.0), wr, rtol=0, atol=1e-16)
 
 
-def test_gamma_from_degrees_of_freedom():
-    # Sec. III: gamma = (D+n+2)/(D+n); the rotational energy n T / 2 adds to
-    # the translational D T / 2.  The workloads map gamma -> n = 2/(gamma-1) - D.
-    for D in (1, 2, 3):
-        for gamma in (1.1, 1.3, 1.4, 5.0 / 3.0):
-            n = 2.0 / (gamma - 1.0) - D
-            assert (D + n + 2) / (D + n) == pytest.approx(gamma, rel=1e-14)
+@pytest.mark.parametrize("kind,D", [(1, 1), (2, 2), (3, 3)])
+@pytest.mark.parametrize("n_rot", [0.0, 2.0, 11.0 / 3.0, 19.0])
+def test_heat_capacity_ratio_from_discrete_equilibria(orc, kind, D, n_rot):
+    """gamma = (D+n+2)/(D+n) (Sec. III) as a property of the discrete
+    equilibria, not of the formula: the internal energy per unit mass of the
+    equilibrium state at rest, (sum_i f^eq xi_i^2/2 + rho (n/2) sum_j g^eq
+    eta_j^2) / rho, differentiated in T gives c_v; the pressure from the
+    second moment, sum_i f^eq xi_x^2, gives R = p / (rho T); gamma = 1 + R/c_v."""
+    c, w, r = orc.lattice(kind)
+    xi = r * c[:, :D].astype(np.float64)
+    eta, _ = orc.rot_lattice()
+    rho, T, h = 1.3, 0.9, 1e-4
+
+    def e_int(Tv):
+        f = orc.feq(kind, rho, [0.0] * D, Tv)
+        g = orc.geq(Tv)
+        return ((f * (xi ** 2).sum(1)).sum() / 2 + rho * (n_rot / 2) * (g * eta ** 2).sum()) / rho
+
+    cv = (e_int(T + h) - e_int(T - h)) / (2 * h)
+    p = (orc.feq(kind, rho, [0.0] * D, T) * xi[:, 0] ** 2).sum()
+    gamma = 1.0 + (p / (rho * T)) / cv
+    assert gamma == pytest.approx((D + n_rot + 2) / (D + n_rot), rel=1e-9)

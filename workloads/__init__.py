@@ -36,7 +36,10 @@ R_PRINTED = 1.1969797752
 
 
 def n_of_gamma(gamma: float, D: int) -> float:
-    return 2.0 / (gamma - 1.0) - D
+    """Rotational degrees of freedom n = 2/(gamma-1) - D; a result within
+    rounding of zero (gamma = 5/3 in 3-D) is exactly zero."""
+    n = 2.0 / (gamma - 1.0) - D
+    return 0.0 if abs(n) < 1e-12 else n
 
 
 def sod_tube(N: int, left, right):
