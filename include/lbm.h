@@ -269,6 +269,22 @@ lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const d
  * written by the end of the launch. */
 lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream);
 
+/* For callers that cannot allocate device memory or instantiate graphs
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): lbm_batch_step without a workspace.  desc->workspace is
+ * ignored (may be NULL); the launch uses a fixed 8 MiB device array of the
+ * library instead, one per device, held until the process ends.  The
+ * schedule kernel re-initialises every word of it that the launch reads, so
+ * the previous call's contents do not matter; but every call on one device
+ * shares the array, so calls that overlap in time on one device (different
+ * streams, or threads) race and must be serialised by the caller.  The two
+ * kernels are launched directly on hip_stream (no graph); no hipMalloc,
+ * hipFree or graph instantiation happens.  Results are those of
+ * lbm_batch_step on the same descriptor, bitwise.  Errors: LBM_EINVAL (as
+ * lbm_batch_step, or lbm_batch_workspace_bytes(desc) above 8 MiB, i.e.
+ * roughly 64 B per tube plus 0.5 B per node), LBM_EDEVICE, LBM_ELAUNCH. */
+lbm_status lbm_batch_step_noalloc(const lbm_batch_desc *desc, void *hip_stream);
+
 /* Release the HIP graph lbm_batch_step keeps for this descriptor on the
  * current device (the library records one per distinct descriptor and device,
  * at most 16, and otherwise keeps them until the process ends).  Call it

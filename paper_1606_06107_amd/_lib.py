@@ -64,6 +64,7 @@ SIGNATURES = {
     "lbm_batch_workspace_bytes": (c_sz, [ctypes.POINTER(LbmBatchDesc)]),
     "lbm_batch_init": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp, c_vp, c_vp, c_vp]),
     "lbm_batch_step": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp]),
+    "lbm_batch_step_noalloc": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp]),
     "lbm_batch_release": (c_i32, [ctypes.POINTER(LbmBatchDesc)]),
     "lbm_batch_moments": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp, c_vp, c_vp, c_vp]),
     "lbm_sur_bf16_bytes": (c_sz, []),

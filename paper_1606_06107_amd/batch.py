@@ -85,6 +85,13 @@ class Batch:
         L.check(self.lib.lbm_batch_step(ctypes.byref(self.desc), self._s()))
         return self
 
+    def step_noalloc(self):
+        """step() through lbm_batch_step_noalloc: the library's fixed device
+        scratch instead of this batch's workspace, direct launches, no
+        allocation.  Same results."""
+        L.check(self.lib.lbm_batch_step_noalloc(ctypes.byref(self.desc), self._s()))
+        return self
+
     def moments(self):
         """Packed FP64 (rho, u, T) device tensors of the current state."""
         dev = self.device

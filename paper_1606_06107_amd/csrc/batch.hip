@@ -825,6 +825,34 @@ bool same_desc(const lbm_batch_desc &x, const lbm_batch_desc &y) {
            x.superstep == y.superstep;
 }
 
+// Scratch of lbm_batch_step_noalloc: the workspace of the batched launch
+// (schedule arrays, counters, chunk queue) in a fixed device array, for
+// callers that cannot allocate.  Each device the library runs on holds its
+// own copy until the process ends; its address on the current device comes
+// from hipGetSymbolAddress (the array's name in host code is not a device
+// address).
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scr_mu;
+void *g_scr_ptr[kMaxDevices] = {};
+
+lbm_status scratch_on_current_device(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return bfail(LBM_EDEVICE, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices) return bfail(LBM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scr_mu);
+    if (!g_scr_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return bfail(LBM_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        g_scr_ptr[dev] = p;
+    }
+    *out = g_scr_ptr[dev];
+    return LBM_OK;
+}
+
 hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s, bool prepare) {
     lbmx::BatchArgs a;
     a.offsets = d->offsets;
@@ -936,6 +964,31 @@ lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream) {
     g_cache.push_back({dev, *desc, exec});
     e = hipGraphLaunch(exec, s);
     if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step_noalloc(const lbm_batch_desc *desc, void *hip_stream) {
+    if (!desc) return bfail(LBM_EINVAL, "batch descriptor is NULL");
+    lbm_batch_desc d = *desc;
+    const size_t need = lbm_batch_workspace_bytes(&d);
+    if (need > kNoAllocScratchBytes)
+        return bfail(LBM_EINVAL, "batch needs " + std::to_string(need) + " bytes of scratch; the no-allocation "
+                                 "entry point has " + std::to_string(kNoAllocScratchBytes));
+    void *scr = nullptr;
+    lbm_status st = scratch_on_current_device(&scr);
+    if (st) return st;
+    d.workspace = scr;
+    st = bvalidate(&d);
+    if (st) return st;
+    Launch L;
+    st = plan(&d, &L);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    // direct launches (no graph: instantiating one allocates); the schedule
+    // kernel re-initialises every scratch word the persistent kernel reads
+    hipError_t e = enqueue_batch(&d, L, s, true);
+    if (e == hipSuccess) e = enqueue_batch(&d, L, s, false);
+    if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("batch launch: ") + hipGetErrorString(e));
     return LBM_OK;
 }
 

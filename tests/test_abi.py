@@ -163,3 +163,18 @@ def test_batch_release_rejects_null(lib):
     L = lib.load()
     assert L.lbm_batch_release(None) == lib.LBM_EINVAL
     assert L.lbm_prepare(None, 5) == lib.LBM_EINVAL
+
+
+def test_batch_noalloc_rejects_oversized_batch(lib):
+    """The fixed scratch holds 8 MiB; a batch needing more is refused before
+    any device work."""
+    L = lib.load()
+    d = lib.LbmBatchDesc()
+    d.abi_version = lib.LBM_ABI_VERSION
+    d.dtype = lib.LBM_F32
+    d.num_instances = 1000
+    d.total_nodes = (1 << 31) - 1
+    assert L.lbm_batch_workspace_bytes(ctypes.byref(d)) > 8 << 20
+    assert L.lbm_batch_step_noalloc(ctypes.byref(d), None) == lib.LBM_EINVAL
+    assert b"scratch" in L.lbm_last_error()
+    assert L.lbm_batch_step_noalloc(None, None) == lib.LBM_EINVAL
