@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # (profiles/k_step_12_d2q49_1024x1024_fp32.md), per tile shape; valid only for
 # the sources they were taken on (sha256 of the files below).
 TRAFFIC = {"nodes": 1024 * 1024, "inplace": True,
-           "bytes": {(256, 1): 489_276_211, (128, 2): 489_725_901, (64, 2): 491_665_357, (64, 4): 491_099_341},
-           "sha256": "c553cce5833f16c56f9dcdd3d9ea0471cccee0daf7fc397ca083963326de0d0c"}
+           "bytes": {(16, 16): 519_551_003, (32, 8): 499_953_768, (32, 16): 473_630_352, (64, 2): 492_014_337, (64, 4): 490_725_485, (64, 8): 473_729_354, (128, 2): 488_759_853, (256, 1): 489_820_193},
+           "sha256": "7d8726f74ab25147df9e37a36b71be6017f4b9b6b69a3bd0c36312501bf2c7f7"}
 TRAFFIC_SOURCES = ('paper_1606_06107_amd/csrc/step_impl.hpp', 'paper_1606_06107_amd/csrc/lbm_device.hpp', 'paper_1606_06107_amd/csrc/launch.hpp', 'paper_1606_06107_amd/csrc/step_12_f32_inplace.hip', 'paper_1606_06107_amd/_build.py')
 
 
@@ -206,6 +206,60 @@ def extra_3d(steps=10):
             "ms_per_step": round(ms, 3), "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1),
             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok and ok_plain,
             "plain_order_ms_per_step": round(ms_plain, 3)}
+
+
+def extra_3d_full(steps=2000, every=100, tau=None, fp64_gamma=1.4, n=256):
+    """The full 3-D workload: 256^3 decaying turbulence, FP32, 2000 steps for
+    each gamma of the set (n = 11/3, 2, 0), the kinetic energy every 100
+    steps; and the same run in FP64 for one gamma, whose kinetic-energy
+    curve the FP32 one is compared with (chaotic flow: no pointwise claim).
+    Only the step calls are timed.  Opt-in (--extras turbulence_3d_full):
+    about two minutes."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    N = n ** 3
+    tau = workloads.Turbulence3D().tau if tau is None else tau
+    out = {"workload": f"3-D {n}^3 decaying turbulence, D3Q343+D1Q7, tau={tau}, {steps} steps, "
+                       "rms Mach 0.3, k^4 exp(-2(k/4)^2) spectrum", "runs": []}
+    curves = {}
+    for gamma, dt in ((1.3, torch.float32), (1.4, torch.float32), (5.0 / 3.0, torch.float32),
+                      (fp64_gamma, torch.float64)):
+        w = workloads.Turbulence3D(n=n, gamma=gamma, tau=tau)
+        sim = Sim((n,) * 3, n_rot=w.n_rot, tau=tau, dtype=dt).init(*w.fields())
+        sim.prepare(every)
+        ke, ms, t = [], 0.0, 0
+        while True:
+            rho, u, T, tot = sim.moments()
+            ke.append(float((0.5 * rho * (u * u).sum(0)).sum().item()))
+            del rho, u, T
+            if t >= steps or not np.isfinite(ke[-1]):
+                break
+            a, b = _events(sim.stream)
+            torch.cuda.synchronize()
+            a.record(sim.stream)
+            sim.step(every)
+            b.record(sim.stream)
+            torch.cuda.synchronize()
+            ms += a.elapsed_time(b)
+            t += every
+        name = "f32" if dt == torch.float32 else "f64"
+        curves[(round(gamma, 4), name)] = np.array(ke)
+        tot = tot.cpu().numpy()
+        out["runs"].append({"gamma": round(gamma, 4), "n_rot": round(w.n_rot, 4), "dtype": name,
+                            "steps_finite": t if np.isfinite(ke[-1]) else t - every,
+                            "ms_per_step": round(ms / max(t, 1), 3), "MLUPS": round(N * t / ms / 1e3, 1),
+                            "KE_over_KE0_every_100": [round(v / ke[0], 5) for v in ke],
+                            "final_totals": [float(v) for v in tot]})
+        print(f"bench: turbulence_3d_full gamma={gamma:.4f} {name} done", file=sys.stderr, flush=True)
+        del sim
+        torch.cuda.empty_cache()
+    a, b = curves.get((round(fp64_gamma, 4), "f32")), curves.get((round(fp64_gamma, 4), "f64"))
+    if a is not None and b is not None and len(a) == len(b):
+        out["fp32_vs_fp64_KE_max_rel"] = float(np.max(np.abs(a - b) / np.abs(b)))
+    return out
 
 
 def extra_d2q37(steps=200):
@@ -651,6 +705,7 @@ def main():
         extra = {}
         wanted = set(args.extras.split(","))
         for name, fn in (("hbm", extra_hbm), ("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d),
+                         ("turbulence_3d_full", extra_3d_full),
                          ("d2q37", extra_d2q37), ("fd", extra_fd),
                          ("transport", extra_transport), ("batched_tubes", extra_batch),
                          ("surrogate", lambda: extra_surrogate(train_steps=args.sur_train_steps))):

@@ -14,8 +14,10 @@ pytestmark = pytest.mark.gpu
 # FP64 accumulation in the reference; rounding-boundary flips of single BF16
 # values make the outputs differ by ~1e-3 relative.
 FWD_TOL = 1e-2   # max|Y_gpu - Y_ref| / max|Y_ref|
-GRAD_TOL = 3e-2  # ||g_gpu - g_ref|| / ||g_ref|| per parameter tensor
-GRAD_ELEM_TOL = 5e-2  # max_k |g_gpu[k] - g_ref[k]| / max_k |g_ref[k]| per parameter tensor
+GRAD_TOL = 1e-2  # ||g_gpu - g_ref|| / ||g_ref|| per parameter tensor
+# max_k |g_gpu[k] - g_ref[k]| / max_k |g_ref[k]| per parameter tensor; measured
+# on MI355X: <= 2.9e-4 (2 x 256 tokens), <= 1.7e-5 (the 32 x 4096 training batch)
+GRAD_ELEM_TOL = 1e-3
 
 
 @pytest.fixture(scope="module")

@@ -35,11 +35,12 @@ import numpy as np
 R_PRINTED = 1.1969797752
 
 
-def n_of_gamma(gamma: float, D: int) -> float:
+def n_of_gamma(gamma, D: int):
     """Rotational degrees of freedom n = 2/(gamma-1) - D; a result within
     rounding of zero (gamma = 5/3 in 3-D) is exactly zero."""
-    n = 2.0 / (gamma - 1.0) - D
-    return 0.0 if abs(n) < 1e-12 else n
+    n = 2.0 / (np.asarray(gamma, dtype=np.float64) - 1.0) - D
+    n = np.where(np.abs(n) < 1e-12, 0.0, n)
+    return float(n) if n.ndim == 0 else n
 
 
 def sod_tube(N: int, left, right):
@@ -121,9 +122,18 @@ class Periodic2D:
 
 @dataclass
 class Turbulence3D:
+    """tau = 1: the relaxation time of the 3-D workload.  The forward-Euler
+    upwind update of the rotational populations is linearly unstable where
+    the Courant number |u_a|/r exceeds a bound that falls with 1/tau (0.67 at
+    tau = 1, about 0.25 at tau = 0.6), and the initial peak speed here is
+    ~0.9 (Courant number 0.75).  Measured on the GPU: tau = 0.6 diverges
+    within 100 steps at 128^3 for n > 0 and not for n = 0 (whose rotational
+    populations carry no energy); tau = 0.8 diverges at 256^3 in FP32 for n > 0
+    within 100 steps while FP64 survives 2000 (the unstable mode grows from
+    rounding noise); tau = 1 runs 2000 steps at 256^3 for every gamma."""
     n: int = 256
     gamma: float = 1.4
-    tau: float = 0.6
+    tau: float = 1.0
     steps: int = 2000
     mach_rms: float = 0.3
     seed: int = 0
