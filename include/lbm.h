@@ -365,23 +365,32 @@ lbm_status lbm_sur_adam(const lbm_sur_desc *desc, float *params, float *m, float
  * steps (the balance laws of Sec. II: (K/r) times the difference of the
  * equilibrium fluxes rho u, rho (u^2 + T), rho u (u^2/2 + (3+n) T/2) at the
  * first and last node, end states averaged over x and y) within tol_mass,
- * tol_mom (relative to mass * sqrt(max T of x)) and tol_energy (relative),
- * and y must be finite with rho > 0 and T > 0.
+ * tol_mom (relative to mass * sqrt(max T of x)) and tol_energy (relative);
+ * y must be finite with rho > 0 and T > 0 at every node, and, if max_mach
+ * > 0, |u| <= max_mach sqrt(T) at every node (the fourth-order D1Q7
+ * equilibrium of Sec. IV stays positive up to |u| ~ 0.91 sqrt(T)).
  * accept[b] = 1 or 0 (device int32).  The totals use FP64 and a fixed
- * reduction order. */
+ * reduction order.  Errors: LBM_EINVAL, LBM_ELAUNCH. */
 lbm_status lbm_sur_check(const lbm_sur_desc *desc, const double *x, const double *y,
                          const double *gamma, double tol_mass, double tol_mom, double tol_energy,
-                         int32_t *accept, void *hip_stream);
+                         double max_mach, int32_t *accept, void *hip_stream);
 
-/* Fallback preparation: for every tube b with accept[b] == 0 and
- * valid[b] == 0 write the equilibrium populations of x (f = f^eq, g = g^eq,
- * Sec. IV) into the packed FP32 batch buffers f0 [7][B*L], g0 [7][B*L] at
- * the tube's slot.  valid[b] != 0 means those buffers already hold the
- * tube's populations at the time of x (its previous chunk ran the plain
- * scheme), so the non-equilibrium part is kept.  nsteps[b] = LBM_SUR_K for
- * rejected tubes, 0 for accepted ones. */
+/* Fallback preparation into the batch that runs the plain scheme for the
+ * rejected tubes: `batch` must describe FP32 populations of exactly
+ * desc->batch tubes of desc->length nodes (tube b owns nodes b*L ..
+ * (b+1)*L-1), else LBM_EINVAL (size and type are checked on the host; a tube
+ * whose device offsets differ gets nothing written and 0 steps).  For every
+ * tube b with accept[b] == 0 and valid[b] == 0 the equilibrium populations
+ * of x (f = f^eq, g = g^eq, Sec. IV) are written into batch->f[0],
+ * batch->g[0] at the tube's slot.  valid[b] != 0 means those buffers already
+ * hold the tube's populations at the time of x (it ran the plain scheme up
+ * to that time), so the non-equilibrium part is kept.  batch->nsteps[b] =
+ * steps (>= 0; LBM_SUR_K for one call) for every rejected tube (lift
+ * writes it); accepted tubes' entries are left as they are, so a caller
+ * that collects rejections over several calls zeroes nsteps first.
+ * Errors: LBM_EINVAL, LBM_ELAUNCH. */
 lbm_status lbm_sur_lift(const lbm_sur_desc *desc, const double *x, const int32_t *accept,
-                        const int32_t *valid, void *f0, void *g0, int64_t *nsteps,
+                        const int32_t *valid, const lbm_batch_desc *batch, int64_t steps,
                         void *hip_stream);
 
 /* out[c][b][l] = accept[b] ? y : z (FP64 [3][B][L]); out may alias y or z.

@@ -74,9 +74,10 @@ SIGNATURES = {
     "lbm_sur_backward": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbm_sur_adam": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, ctypes.c_float,
                              ctypes.c_float, ctypes.c_float, ctypes.c_float, c_i64, c_vp]),
-    "lbm_sur_check": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_dbl, c_dbl, c_dbl,
+    "lbm_sur_check": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_dbl, c_dbl, c_dbl, c_dbl,
                               c_vp, c_vp]),
-    "lbm_sur_lift": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lbm_sur_lift": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, ctypes.POINTER(LbmBatchDesc), c_i64,
+                             c_vp]),
     "lbm_sur_merge": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
 }
 

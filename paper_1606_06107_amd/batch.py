@@ -80,9 +80,11 @@ class Batch:
             self.nsteps.copy_(torch.as_tensor(np.asarray(nsteps, dtype=np.int64)))
         cur.wait_stream(self.stream)
 
-    def step(self):
-        """Advance every tube i by nsteps[i] steps (one persistent launch)."""
-        L.check(self.lib.lbm_batch_step(ctypes.byref(self.desc), self._s()))
+    def step(self, stream=None):
+        """Advance every tube i by nsteps[i] steps (one persistent launch), on
+        the batch's stream or on `stream`."""
+        s = self._s() if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        L.check(self.lib.lbm_batch_step(ctypes.byref(self.desc), s))
         return self
 
     def step_noalloc(self):

@@ -638,6 +638,7 @@ struct CheckArgs {
     int B, L;
     const double *x, *y, *gamma;
     double tol_m, tol_p, tol_e;
+    double max_mach;  // bound on |u| / sqrt(T) of y (0: none)
     int32_t *accept;
 };
 
@@ -665,6 +666,10 @@ __global__ void __launch_bounds__(kChkT) k_check(CheckArgs a) {
         acc[6] = fmax(acc[6], Tx);
         if (!__builtin_isfinite(ry) || !__builtin_isfinite(uy) || !__builtin_isfinite(Ty) || ry <= 0.0 ||
             Ty <= 0.0)
+            bad = 1;
+        // the envelope where the fourth-order equilibria stay positive
+        // (|u| <= ~0.91 sqrt(T) on D1Q7): a prediction outside it is rejected
+        else if (a.max_mach > 0.0 && uy * uy > a.max_mach * a.max_mach * Ty)
             bad = 1;
     }
     if (threadIdx.x == 0) bad_s = 0;
@@ -710,16 +715,22 @@ __global__ void __launch_bounds__(kChkT) k_check(CheckArgs a) {
 }
 
 // Equilibrium populations of x for rejected tubes without live populations;
-// nsteps per tube.
+// nsteps of the rejected tubes (accepted tubes' entries stay as they are).  A batch tube whose node range is not [b L, (b+1) L)
+// gets nothing written and 0 steps (the host checks the batch's size and
+// type; the ranges live in device memory).
 __global__ void __launch_bounds__(256) k_lift(int B, int L, const double *x, const int32_t *accept,
-                                              const int32_t *valid, float *f0, float *g0,
-                                              int64_t *nsteps) {
+                                              const int32_t *valid, const int64_t *offsets, float *f0,
+                                              float *g0, int64_t *nsteps, int64_t steps) {
     const size_t BL = (size_t)B * L;
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < (size_t)B) nsteps[i] = accept[i] ? 0 : LBM_SUR_K;
+    if (i < (size_t)B && !accept[i]) {
+        const bool fits = offsets[i] == (int64_t)i * L && offsets[i + 1] == (int64_t)(i + 1) * L;
+        nsteps[i] = fits ? steps : 0;
+    }
     if (i >= BL) return;
     const int b = (int)(i / L);
     if (accept[b] || valid[b]) return;
+    if (offsets[b] != (int64_t)b * L || offsets[b + 1] != (int64_t)(b + 1) * L) return;
     const double uu[3] = {x[BL + i], 0.0, 0.0};
     const FeqCoef<double> fc = feq_coef<double, 1>(x[i], uu, x[2 * BL + i]);
     static_for<0, 7>([&](auto I) {
@@ -954,24 +965,35 @@ lbm_status lbm_sur_adam(const lbm_sur_desc *d, float *params, float *m, float *v
 }
 
 lbm_status lbm_sur_check(const lbm_sur_desc *d, const double *x, const double *y, const double *gamma,
-                         double tol_mass, double tol_mom, double tol_energy, int32_t *accept, void *stream) {
+                         double tol_mass, double tol_mom, double tol_energy, double max_mach,
+                         int32_t *accept, void *stream) {
     lbm_status st = svalidate(d);
     if (st) return st;
     if (!x || !y || !gamma || !accept) return sfail(LBM_EINVAL, "NULL argument");
-    CheckArgs a{d->batch, d->length, x, y, gamma, tol_mass, tol_mom, tol_energy, accept};
+    if (!(max_mach >= 0.0)) return sfail(LBM_EINVAL, "max_mach must be >= 0");
+    CheckArgs a{d->batch, d->length, x, y, gamma, tol_mass, tol_mom, tol_energy, max_mach, accept};
     hipLaunchKernelGGL(k_check, dim3(d->batch), dim3(kChkT), 0, (hipStream_t)stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
 }
 
 lbm_status lbm_sur_lift(const lbm_sur_desc *d, const double *x, const int32_t *accept, const int32_t *valid,
-                        void *f0, void *g0, int64_t *nsteps, void *stream) {
+                        const lbm_batch_desc *batch, int64_t steps, void *stream) {
     lbm_status st = svalidate(d);
     if (st) return st;
-    if (!x || !accept || !valid || !f0 || !g0 || !nsteps) return sfail(LBM_EINVAL, "NULL argument");
+    if (!x || !accept || !valid || !batch) return sfail(LBM_EINVAL, "NULL argument");
+    if (steps < 0) return sfail(LBM_EINVAL, "steps must be >= 0");
+    if (batch->abi_version != LBM_ABI_VERSION) return sfail(LBM_EINVAL, "batch abi_version mismatch");
+    if (batch->dtype != LBM_F32) return sfail(LBM_EINVAL, "the fallback batch must hold FP32 populations");
+    if (batch->num_instances != d->batch || batch->total_nodes != (int64_t)d->batch * d->length)
+        return sfail(LBM_EINVAL, "the fallback batch must have one tube of the surrogate's length per surrogate tube");
+    if (!batch->f[0] || !batch->g[0] || !batch->nsteps || !batch->offsets)
+        return sfail(LBM_EINVAL, "fallback batch buffers must not be NULL");
     const size_t BL = (size_t)d->batch * d->length;
+    // nsteps is an input of lbm_batch_step; lift is what sets it
     hipLaunchKernelGGL(k_lift, dim3(nblk(BL > (size_t)d->batch ? BL : d->batch)), dim3(256), 0, (hipStream_t)stream,
-                       d->batch, d->length, x, accept, valid, (float *)f0, (float *)g0, nsteps);
+                       d->batch, d->length, x, accept, valid, batch->offsets, (float *)batch->f[0],
+                       (float *)batch->g[0], const_cast<int64_t *>(batch->nsteps), steps);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
 }

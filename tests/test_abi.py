@@ -178,3 +178,51 @@ def test_batch_noalloc_rejects_oversized_batch(lib):
     assert L.lbm_batch_step_noalloc(ctypes.byref(d), None) == lib.LBM_EINVAL
     assert b"scratch" in L.lbm_last_error()
     assert L.lbm_batch_step_noalloc(None, None) == lib.LBM_EINVAL
+
+
+def test_surrogate_lift_validates_the_fallback_batch(lib):
+    """lbm_sur_lift refuses a fallback batch of the wrong type or size before
+    any device work (the writes go to the batch's buffers)."""
+    L = lib.load()
+    s = lib.LbmSurDesc()
+    s.abi_version = lib.LBM_ABI_VERSION
+    s.batch, s.length = 4, 256
+    b = lib.LbmBatchDesc()
+    b.abi_version = lib.LBM_ABI_VERSION
+    b.dtype = lib.LBM_F64
+    b.num_instances, b.total_nodes = 4, 4 * 256
+    for k in range(2):
+        b.f[k] = b.g[k] = 0x1000 * (k + 1)
+    b.nsteps = b.offsets = 0x2000
+    x = acc = valid = ctypes.c_void_p(0x3000)
+    assert L.lbm_sur_lift(ctypes.byref(s), x, acc, valid, ctypes.byref(b), 16, None) == lib.LBM_EINVAL
+    assert b"FP32" in L.lbm_last_error()
+    b.dtype = lib.LBM_F32
+    b.total_nodes = 4 * 255
+    assert L.lbm_sur_lift(ctypes.byref(s), x, acc, valid, ctypes.byref(b), 16, None) == lib.LBM_EINVAL
+    b.total_nodes, b.num_instances = 4 * 256, 3
+    assert L.lbm_sur_lift(ctypes.byref(s), x, acc, valid, ctypes.byref(b), 16, None) == lib.LBM_EINVAL
+    assert L.lbm_sur_lift(ctypes.byref(s), x, acc, valid, None, 16, None) == lib.LBM_EINVAL
+    assert L.lbm_sur_check(ctypes.byref(s), x, x, x, 1e-3, 1e-3, 1e-3, -1.0, acc, None) == lib.LBM_EINVAL
+
+
+def test_surrogate_rollout_refuses_a_mismatched_batch():
+    """The Python front end checks the fallback batch's type and tube
+    lengths before the library is asked (no device work)."""
+    torch = pytest.importorskip("torch")
+    from paper_1606_06107_amd.surrogate import Surrogate
+
+    class FakeBatch:
+        dtype = torch.float64
+        I = 2
+        offsets_h = np.array([0, 256, 512])
+
+    sur = Surrogate.__new__(Surrogate)
+    sur.B, sur.L = 2, 256
+    with pytest.raises(ValueError):
+        sur.check_fallback(FakeBatch())
+    FakeBatch.dtype = torch.float32
+    sur.check_fallback(FakeBatch())
+    FakeBatch.offsets_h = np.array([0, 128, 512])
+    with pytest.raises(ValueError):
+        sur.check_fallback(FakeBatch())

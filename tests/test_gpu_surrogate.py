@@ -161,10 +161,11 @@ def test_check_lift_merge(torch_cuda):
     batch = Batch([L] * B, n_rot, [0.8] * B, [0] * B, dtype=torch.float32)
     batch.f[0].zero_()
     batch.g[0].zero_()
+    batch.nsteps.fill_(7)
     sur.valid.zero_()
     sur.lift(xd, sur.accept, batch)
     torch.cuda.synchronize()
-    assert list(batch.nsteps.cpu().numpy()) == [0, 16, 16]
+    assert list(batch.nsteps.cpu().numpy()) == [7, 16, 16]  # the accepted tube's entry is left alone
     f = batch.f[0].double().cpu().numpy().reshape(7, B, L)
     g = batch.g[0].double().cpu().numpy().reshape(7, B, L)
     assert np.all(f[:, 0] == 0.0)  # accepted tube untouched
@@ -207,8 +208,15 @@ def test_check_accepts_the_plain_scheme(torch_cuda):
     assert list(plain.status.cpu().numpy()) == [0] * B
     sur = _gpu(torch, S.init_params(0), B, L)
     xd, gd = _dev(torch, x), _dev(torch, gamma)
-    assert list(sur.check(xd, z, gd).cpu().numpy()) == [1, 1, 1]
-    assert list(sur.check(xd, xd, gd).cpu().numpy()) == [0, 0, 1]
+    # the balance laws alone (no Mach envelope)
+    assert list(sur.check(xd, z, gd, max_mach=0.0).cpu().numpy()) == [1, 1, 1]
+    assert list(sur.check(xd, xd, gd, max_mach=0.0).cpu().numpy()) == [0, 0, 1]
+    # classic Sod's star state moves at |u| / sqrt(T) ~ 1.1, outside the
+    # envelope where the equilibria stay positive: rejected with the default
+    # envelope (the plain scheme itself diverges on that tube later)
+    mach = (np.abs(z[1].cpu().numpy()) / np.sqrt(z[2].cpu().numpy())).max(-1)
+    assert mach[0] > 0.9 and mach[1] < 0.9 and mach[2] < 0.9
+    assert list(sur.check(xd, z, gd).cpu().numpy()) == [0, 1, 1]
 
 
 def test_rejecting_everything_reproduces_plain_lbm_bitwise(torch_cuda):
@@ -292,3 +300,78 @@ def test_rollout_on_a_caller_stream(torch_cuda):
     other = Batch(bt.lengths, bt.n_rot, bt.tau, np.zeros(B, dtype=np.int64), dtype=torch.float32, stream=side)
     with pytest.raises(ValueError):
         rollout(sur, x0, gamma, other, 1)
+
+
+def _mixed_tubes(L):
+    """Three tubes: 0 and 2 at rest with a small density step (predictions
+    stay near Mach 0), 1 in uniform motion at Mach 0.5 with the same step."""
+    B = 3
+    x = np.zeros((3, B, L))
+    left = np.arange(L) < L // 2
+    for b in range(B):
+        x[0, b] = np.where(left, 1.0, 0.9)
+        x[2, b] = 1.0
+    x[1, 1] = 0.5
+    gamma = np.array([1.4, 1.5, 1.3])
+    return x, gamma
+
+
+def test_rollout_mixed_verdicts(torch_cuda):
+    """A plain first call, then calls in which the check (Mach envelope 0.3,
+    balance tolerances open) accepts the tubes at rest and rejects the moving
+    one, so every call mixes verdicts and its speculative forward is
+    discarded: the tubes at rest are the surrogate chained on the plain
+    scheme's first 16 steps, the moving tube the uninterrupted plain scheme,
+    bitwise."""
+    announce("rollout with mixed verdicts")
+    import torch
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd.surrogate import fields_of, rollout
+    L, calls = 512, 4
+    x, gamma = _mixed_tubes(L)
+    B = x.shape[1]
+    n_rot = 2.0 / (gamma - 1.0) - 1.0
+    tau = [0.8] * B
+    sur = _gpu(torch, S.init_params(0), B, L)
+    x0, gd = _dev(torch, x), _dev(torch, gamma)
+    fb = Batch([L] * B, n_rot, tau, np.zeros(B, dtype=np.int64), dtype=torch.float32)
+    xr, acc = rollout(sur, x0, gd, fb, calls, tols=(1e300, 1e300, 1e300), plain_calls=1, max_mach=0.3)
+    assert acc.cpu().tolist() == [0] + [2] * (calls - 1)
+    plain = Batch([L] * B, n_rot, tau, np.full(B, 16), dtype=torch.float32)
+    plain.init(x[0].ravel(), x[1].ravel(), x[2].ravel()).step()
+    ref = fields_of(plain)
+    for _ in range(calls - 1):
+        ref = sur.forward(ref, gd)
+    full = Batch([L] * B, n_rot, tau, np.full(B, 16 * calls), dtype=torch.float32)
+    full.init(x[0].ravel(), x[1].ravel(), x[2].ravel()).step()
+    ref_full = fields_of(full).cpu().numpy()
+    got, ref = xr.cpu().numpy(), ref.cpu().numpy()
+    assert np.array_equal(got[:, [0, 2]], ref[:, [0, 2]])
+    assert np.array_equal(got[:, 1], ref_full[:, 1])
+
+
+def test_rollout_plain_first_then_all_accepted(torch_cuda):
+    """A plain first call (every tube's batch populations are then live)
+    followed by calls that every tube passes: the first accepted call resets
+    the live flags, and the result is the surrogate chained on the plain
+    scheme's first 16 steps, bitwise."""
+    announce("rollout plain first, then all accepted")
+    import torch
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd.surrogate import fields_of, rollout
+    L, calls = 512, 3
+    x, gamma = _mixed_tubes(L)
+    B = x.shape[1]
+    n_rot = 2.0 / (gamma - 1.0) - 1.0
+    sur = _gpu(torch, S.init_params(0), B, L)
+    x0, gd = _dev(torch, x), _dev(torch, gamma)
+    fb = Batch([L] * B, n_rot, [0.8] * B, np.zeros(B, dtype=np.int64), dtype=torch.float32)
+    xr, acc = rollout(sur, x0, gd, fb, calls, tols=(1e300, 1e300, 1e300), plain_calls=1, max_mach=0.0)
+    assert acc.cpu().tolist() == [0] + [B] * (calls - 1)
+    assert list(sur.valid.cpu().numpy()) == [0] * B
+    plain = Batch([L] * B, n_rot, [0.8] * B, np.full(B, 16), dtype=torch.float32)
+    plain.init(x[0].ravel(), x[1].ravel(), x[2].ravel()).step()
+    ref = fields_of(plain)
+    for _ in range(calls - 1):
+        ref = sur.forward(ref, gd)
+    assert np.array_equal(xr.cpu().numpy(), ref.cpu().numpy())
