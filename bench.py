@@ -100,27 +100,39 @@ def cpu_baseline(nx, ny, steps, threads, single=(512, 512, 30)):
 
 
 def copy_bandwidth(mbytes, reps=10):
-    """Device-to-device copy of `mbytes` MB (torch's copy kernel), GB/s
-    counting the bytes read plus the bytes written; median of `reps`."""
+    """Device-to-device copy of `mbytes` MB with the library's plain copy
+    kernel (lbm_stream_copy), GB/s counting the bytes read plus the bytes
+    written; median of `reps`.  Also torch's copy of the same buffers."""
+    import ctypes
+
     import torch
-    n = int(mbytes * 1e6) // 4
+
+    from paper_1606_06107_amd import _lib
+    lib = _lib.load()
+    n = int(mbytes * 1e6) // 16 * 4
     src = torch.ones(n, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    ts = []
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        dst.copy_(src)
-        b.record()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("lbm_stream_copy", lambda: _lib.check(lib.lbm_stream_copy(
+            ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n * 4,
+            ctypes.c_void_p(stream.cuda_stream)))), ("torch", lambda: dst.copy_(src))):
+        fn()
         torch.cuda.synchronize()
-        ts.append(a.elapsed_time(b))
-    ts.sort()
-    ms = ts[len(ts) // 2]
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ts.sort()
+        out[name] = round(2 * n * 4 / (ts[len(ts) // 2] * 1e-3) / 1e9, 1)
+    assert bool(torch.equal(dst, src))
     del src, dst
     torch.cuda.empty_cache()
-    return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def _events(stream):
@@ -691,7 +703,8 @@ def main():
     achieved_gbs = N * bytes_per_node / (ms_per_step * 1e-3) / 1e9
     del sim
     torch.cuda.empty_cache()
-    copy_gbs = copy_bandwidth(1024)  # 1 GB: well beyond the memory-side cache
+    copy = copy_bandwidth(2048)  # 2 GB each way: well beyond the memory-side cache
+    copy_gbs = copy["lbm_stream_copy"]
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -714,7 +727,7 @@ def main():
                    "tile": list(used_tile)},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "copy_GBps": copy_gbs,
+                     "traffic": traffic, "copy_GBps": copy_gbs, "torch_copy_GBps": copy["torch"],
                      "frac_of_copy": round(achieved_gbs / copy_gbs, 4)},
         "checks": {"finite": finite, "mass_drift": mass_drift, "momentum_drift": mom_drift,
                    "energy_drift_n3": energy_drift, "wall_s": round(wall, 3)},
@@ -735,6 +748,8 @@ def main():
             print(f"bench: {name}", file=sys.stderr, flush=True)
             extra[name] = fn()
             torch.cuda.empty_cache()
+        for row in extra.get("hbm", {}).get("rows", []):
+            row["frac_of_copy"] = round(row["GBps"] / copy_gbs, 4)
         out["extra"] = extra
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))

@@ -211,6 +211,14 @@ lbm_status lbm_destroy(lbm_sim sim);
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbm_last_error(void);
 
+/* Plain device-to-device copy of `bytes` (a multiple of 16; both buffers
+ * 16-byte aligned) on hip_stream: one 16-byte load and store per thread in
+ * one pass.  Not part of the scheme: the measured memory-bandwidth reference
+ * that the step kernels' achieved bandwidth is set against (the HBM peak of
+ * the data sheet is not reached by any copy).  Errors: LBM_EINVAL,
+ * LBM_ELAUNCH. */
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* Lattice constants the library computes with: Q, r, and (if not NULL) the
  * weights w[Q] and velocities c[Q][3] (integers) of the population slots in
  * storage order (populations[Q][N] of lbm_populations / lbm_init_populations;

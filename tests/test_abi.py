@@ -226,3 +226,11 @@ def test_surrogate_rollout_refuses_a_mismatched_batch():
     FakeBatch.offsets_h = np.array([0, 128, 512])
     with pytest.raises(ValueError):
         sur.check_fallback(FakeBatch())
+
+
+def test_stream_copy_rejects_unaligned(lib):
+    L = lib.load()
+    assert L.lbm_stream_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 24, None) == lib.LBM_EINVAL
+    assert L.lbm_stream_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 32, None) == lib.LBM_EINVAL
+    assert L.lbm_stream_copy(None, ctypes.c_void_p(0x2000), 32, None) == lib.LBM_EINVAL
+    assert L.lbm_stream_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 0, None) == lib.LBM_OK

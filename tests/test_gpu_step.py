@@ -417,3 +417,18 @@ def test_d2q37_paper_shock_tube_table3(torch_cuda, orc):
         # order), so the error values agree to ~1e-11 absolute
         assert abs(e[k] - eo[k]) <= 1e-9, (k, e[k], eo[k])
         assert table[k] / 2.0 <= e[k] <= 2.0 * table[k], (k, e[k], table[k])
+
+
+def test_stream_copy(torch_cuda):
+    """The bandwidth reference kernel copies exactly (ragged last block)."""
+    import ctypes
+    import torch
+    from paper_1606_06107_amd import _lib
+    announce("stream copy")
+    lib = _lib.load()
+    src = torch.randn(4 * 1000003, device="cuda")
+    dst = torch.zeros_like(src)
+    _lib.check(lib.lbm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                   src.numel() * 4, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
