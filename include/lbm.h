@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 typedef int32_t lbm_status;
 enum {
@@ -80,6 +80,17 @@ typedef struct {
     double n_rot;        /* rotational degrees of freedom n >= 0 (real);
                             gamma = (D+n+2)/(D+n) */
     double tau;          /* BGK relaxation time in time steps, tau > 0.5 */
+    int32_t g_substeps;  /* 0 or 1: the rotational update of Sec. V A as written
+                            (one forward-Euler upwind step with Courant number
+                            u_a / r).  m in [2, 64]: its advection in m sub-steps
+                            of Courant number u_a / (m r), relaxation once per
+                            step -- the update is linearly unstable beyond a
+                            Courant number that falls with 1/tau (0.67 at tau =
+                            1, 0.375 at tau = 2/3), which strong shocks exceed.
+                            Runs a plain one-node-per-thread path, ping-pong
+                            only (no in-place streaming, no finite-difference
+                            update), with 17 N population values of extra
+                            workspace */
     void *f[2];          /* two device buffers of Q*N values of dtype (ping-pong);
                             with in-place streaming (lbm_set_inplace) only f[0]
                             is used, but both must be given.  The order of the
@@ -88,7 +99,8 @@ typedef struct {
                             lbm_populations / lbm_init_populations */
     void *g[2];          /* two device buffers [7][N] of dtype (ping-pong) */
     void *workspace;     /* device scratch of lbm_workspace_bytes() bytes, 256-B
-                            aligned (reduction partials); caller-owned */
+                            aligned (reduction partials, the monitor's row
+                            counter, sub-step buffers); caller-owned */
 } lbm_desc;
 
 typedef struct lbm_sim_s *lbm_sim; /* opaque host handle; owns no device memory */

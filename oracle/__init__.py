@@ -55,7 +55,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("lattice", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("bc", ctypes.c_int32 * 3),
                 ("n_rot", ctypes.c_double), ("tau", ctypes.c_double),
-                ("fd_courant", ctypes.c_double)]
+                ("fd_courant", ctypes.c_double), ("g_substeps", ctypes.c_int32)]
 
 
 _lib = None
@@ -135,10 +135,13 @@ class Grid:
     """A grid of nodes with one lattice, boundary conditions, n and tau.
     fd_courant = 0: the collide-and-stream update; lambda > 0: the
     finite-difference update of Sec. V A for f as well, with time step
-    lambda times the streaming step (tau stays in streaming steps)."""
+    lambda times the streaming step (tau stays in streaming steps).
+    g_substeps = m > 1 splits the rotational advection into m sub-steps of
+    Courant number u_a / (m r) (not the paper's update: a diagnostic that
+    separates its Courant limit from other causes of divergence)."""
 
     def __init__(self, lattice_kind: int, shape, bc=(PERIODIC, PERIODIC, PERIODIC),
-                 n_rot: float = 0.0, tau: float = 1.0, fd_courant: float = 0.0):
+                 n_rot: float = 0.0, tau: float = 1.0, fd_courant: float = 0.0, g_substeps: int = 1):
         D = _DIMOF[lattice_kind]
         shape = tuple(int(s) for s in shape)
         assert len(shape) == D, "shape must have one entry per spatial dimension"
@@ -149,7 +152,7 @@ class Grid:
         self.n_rot, self.tau = float(n_rot), float(tau)
         self.fd_courant = float(fd_courant)
         self._g = _Grid(D, lattice_kind, (ctypes.c_int64 * 3)(*n), (ctypes.c_int32 * 3)(*bcs),
-                        self.n_rot, self.tau, self.fd_courant)
+                        self.n_rot, self.tau, self.fd_courant, int(g_substeps))
 
     def init_eq(self, rho, u, T):
         """f = f^eq(rho, u, T), g = g^eq(T) at every node.  u is [D][N]."""

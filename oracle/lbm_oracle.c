@@ -297,6 +297,11 @@ typedef struct {
                            populations (reading A); lambda > 0: the finite-difference
                            update written in Sec. V A (reading B) with time step
                            lambda / r, i.e. lambda times the streaming step */
+    int32_t g_substeps; /* <= 1: the rotational update of Sec. V A as written;
+                           m > 1: its advection in m sub-steps of Courant number
+                           nu_a / m (relaxation once per step), a device outside
+                           the paper used to tell the advection's Courant limit
+                           from other causes of divergence */
 } orc_grid;
 
 typedef struct {
@@ -501,6 +506,56 @@ static void one_step_fd(const orc_grid *G, const lat_t *L, double *f, double *g,
     }
 }
 
+/* One time step with the rotational advection split into m sub-steps:
+ * g(t+1) = A^m g(t) - omega (g(t) - g^eq(T)), where A is the forward-Euler
+ * upwind advection of Sec. V A with Courant numbers nu_a / m and the fluid
+ * velocity of time t.  For m = 1 this is the update of one_step.  u: N*3
+ * scratch, gt: 7*N scratch. */
+static void one_step_sub(const orc_grid *G, const lat_t *L, double *f, double *g, double *fs,
+                         double *gs, int m, double *u3, double *gt)
+{
+    int64_t N = nnodes(G);
+    double omega = 1.0 / G->tau;
+    int64_t N0 = G->n[0], N1 = G->n[1];
+    for (int64_t x = 0; x < N; ++x) {
+        double fn[ORC_MAXQ], gn[7], fe[ORC_MAXQ], ge[7], u[3] = {0, 0, 0}, rho, T;
+        for (int i = 0; i < L->Q; ++i) fn[i] = f[i * N + x];
+        for (int j = 0; j < 7; ++j) gn[j] = g[j * N + x];
+        node_moments(L, G->n_rot, fn, gn, &rho, u, &T, NULL);
+        orc_feq(L->D, L->Q, L->c, L->w, L->r, rho, u, T, fe);
+        geq_on(L->eta, L->wr, T, ge);
+        for (int i = 0; i < L->Q; ++i) fs[i * N + x] = fn[i] - omega * (fn[i] - fe[i]);
+        for (int j = 0; j < 7; ++j) gs[j * N + x] = omega * (gn[j] - ge[j]);  /* relaxation term */
+        for (int d = 0; d < 3; ++d) u3[d * N + x] = u[d];
+    }
+    for (int s = 0; s < m; ++s) {
+        for (int64_t x = 0; x < N; ++x) {
+            int64_t xyz[3] = {x % N0, (x / N0) % N1, x / (N0 * N1)};
+            for (int j = 0; j < 7; ++j) {
+                double adv = 0.0;
+                for (int a = 0; a < L->D; ++a) {
+                    double nu = u3[a * N + x] / L->r / m;
+                    adv += nu * upwind3(G, g + j * N, xyz, a, nu);
+                }
+                gt[j * N + x] = g[j * N + x] - adv;
+            }
+        }
+        memcpy(g, gt, sizeof(double) * 7 * (size_t)N);
+    }
+    for (int64_t x = 0; x < N; ++x) {
+        int64_t xyz[3] = {x % N0, (x / N0) % N1, x / (N0 * N1)};
+        for (int i = 0; i < L->Q; ++i) {
+            int64_t q[3];
+            for (int d = 0; d < 3; ++d) {
+                int cd = (d < L->D) ? L->c[i * 3 + d] : 0;
+                q[d] = wrap_or_clamp(xyz[d] - cd, G->n[d], G->bc[d]);
+            }
+            f[i * N + x] = fs[i * N + q[0] + N0 * (q[1] + N1 * q[2])];
+        }
+        for (int j = 0; j < 7; ++j) g[j * N + x] -= gs[j * N + x];
+    }
+}
+
 /* Advance nsteps time steps in place.  fs/gs: caller scratch, same sizes as f/g. */
 int orc_step(const orc_grid *G, double *f, double *g, double *fs, double *gs, int64_t nsteps)
 {
@@ -513,6 +568,20 @@ int orc_step(const orc_grid *G, double *f, double *g, double *fs, double *gs, in
         return 0;
     }
     if (G->tau <= 0.5) return -2;
+    if (G->g_substeps > 1) {
+        int64_t N = nnodes(G);
+        double *u3 = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+        double *gt = (double *)malloc(sizeof(double) * 7 * (size_t)N);
+        if (!u3 || !gt) {
+            free(u3);
+            free(gt);
+            return -4;
+        }
+        for (int64_t s = 0; s < nsteps; ++s) one_step_sub(G, &L, f, g, fs, gs, G->g_substeps, u3, gt);
+        free(u3);
+        free(gt);
+        return 0;
+    }
     for (int64_t s = 0; s < nsteps; ++s) one_step(G, &L, f, g, fs, gs);
     return 0;
 }

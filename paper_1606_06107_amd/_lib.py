@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbmx.so")
 
-LBM_ABI_VERSION = 1
+LBM_ABI_VERSION = 2
 LBM_OK, LBM_EINVAL, LBM_EDEVICE, LBM_ENOMEM, LBM_EUNSUPPORTED, LBM_ELAUNCH = range(6)
 LBM_D1Q7, LBM_D2Q49, LBM_D3Q343, LBM_D2Q37 = 1, 2, 3, 4
 LBM_F32, LBM_F64 = 0, 1
@@ -23,7 +23,7 @@ c_i32, c_i64, c_dbl, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_doubl
 class LbmDesc(ctypes.Structure):
     _fields_ = [("abi_version", c_i32), ("dim", c_i32), ("n", c_i64 * 3), ("lattice", c_i32),
                 ("dtype", c_i32), ("bc", c_i32 * 3), ("n_rot", c_dbl), ("tau", c_dbl),
-                ("f", c_vp * 2), ("g", c_vp * 2), ("workspace", c_vp)]
+                ("g_substeps", c_i32), ("f", c_vp * 2), ("g", c_vp * 2), ("workspace", c_vp)]
 
 
 class LbmBatchDesc(ctypes.Structure):

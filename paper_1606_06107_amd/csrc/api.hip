@@ -88,6 +88,15 @@ size_t monitor_slot_offset(const lbm_desc *d) {
     return ((rows * (2 + d->dim) * sizeof(double) + 255) / 256) * 256;
 }
 
+// Sub-stepped rotational advection (g_substeps > 1): 17 N population values
+// of scratch after the counter.
+size_t substep_offset(const lbm_desc *d) { return monitor_slot_offset(d) + 256; }
+size_t substep_bytes(const lbm_desc *d) {
+    if (d->g_substeps <= 1) return 0;
+    const size_t N = (size_t)(d->n[0] * d->n[1] * d->n[2]);
+    return ((17 * N * (d->dtype == LBM_F32 ? 4 : 8) + 255) / 256) * 256;
+}
+
 lbm_status validate(const lbm_desc *d) {
     if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
     if (d->abi_version != LBM_ABI_VERSION)
@@ -113,6 +122,7 @@ lbm_status validate(const lbm_desc *d) {
         return fail(LBM_EINVAL, "N * sizeof(population) must be < 2^32 bytes per population");
     if (!(d->n_rot >= 0.0) || !isfinite(d->n_rot)) return fail(LBM_EINVAL, "n_rot must be >= 0");
     if (!(d->tau > 0.5) || !isfinite(d->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
+    if (d->g_substeps < 0 || d->g_substeps > 64) return fail(LBM_EINVAL, "g_substeps must be in [0, 64]");
     if (!d->f[0] || !d->f[1] || !d->g[0] || !d->g[1])
         return fail(LBM_EINVAL, "population buffers must not be NULL");
     if (d->f[0] == d->f[1] || d->g[0] == d->g[1] || d->f[0] == d->g[0] || d->f[1] == d->g[1])
@@ -209,9 +219,35 @@ hipError_t enqueue_step_fd(lbm_sim s, hipStream_t st) {
     return hipSuccess;
 }
 
+lbmx::FieldArgs field_args(lbm_sim s);
+
+// Enqueue one time step with the rotational advection in sub-steps.
+hipError_t enqueue_step_sub(lbm_sim s, hipStream_t st) {
+    const lbm_desc &d = s->d;
+    const lbmx::FieldArgs a = field_args(s);
+    if (s->mon_every > 0 && s->t % s->mon_every == 0) {  // totals of time t
+        lbmx::FieldArgs fa = a;
+        fa.partials = (double *)d.workspace;
+        int nb = 0;
+        hipError_t e = lbmx::launch_fields(d.dtype, d.dim, kind_of(d.lattice), fa, &nb, st);
+        if (e == hipSuccess)
+            e = lbmx::launch_reduce_series((const double *)d.workspace, nb, 2 + d.dim, s->mon_series, s->mon_cap,
+                                           monitor_slot(s), st);
+        if (e != hipSuccess) return e;
+    }
+    void *scratch = static_cast<char *>(d.workspace) + substep_offset(&d);
+    hipError_t e = lbmx::launch_step_sub(d.dtype, d.dim, kind_of(d.lattice), a, d.f[s->fcur ^ 1], d.g[s->gcur ^ 1],
+                                         scratch, d.g_substeps, 1.0 / d.tau, st);
+    if (e != hipSuccess) return e;
+    advance(s, 1);
+    s->t += 1;
+    return hipSuccess;
+}
+
 // Enqueue one time step on stream st and advance the host-side state.
 hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
     if (s->fd > 0.0) return enqueue_step_fd(s, st);
+    if (s->d.g_substeps > 1) return enqueue_step_sub(s, st);
     const lbm_desc &d = s->d;
     lbmx::StepArgs a;
     a.f_in = d.f[s->fcur];
@@ -293,7 +329,7 @@ lbm_status make_sim(const lbm_desc *desc, void *stream, lbm_sim *out) {
     s->d = *desc;
     s->stream = (hipStream_t)stream;
     default_tile(desc->dim, s->tile);
-    s->inplace = inplace_possible(*desc) ? 1 : 0;
+    s->inplace = inplace_possible(*desc) && desc->g_substeps <= 1 ? 1 : 0;
     s->blocked = blocked_possible(*desc) ? 1 : 0;
     if (hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess) {
         delete s;
@@ -356,7 +392,7 @@ size_t lbm_workspace_bytes(const lbm_desc *desc) {
     if (!desc || desc->dim < 1 || desc->dim > 3) return 0;
     for (int a = 0; a < 3; ++a)
         if (desc->n[a] < 1) return 0;
-    return monitor_slot_offset(desc) + 256;
+    return substep_offset(desc) + substep_bytes(desc);
 }
 
 lbm_status lbm_init(const lbm_desc *desc, const double *rho, const double *u, const double *T,
@@ -502,6 +538,8 @@ lbm_status lbm_set_inplace(lbm_sim s, int32_t enable) {
         return fail(LBM_EINVAL, "the streaming scheme can only be chosen before the first step");
     if (enable && !inplace_possible(s->d))
         return fail(LBM_EUNSUPPORTED, "in-place streaming needs a 1-D or 2-D grid periodic in every axis");
+    if (enable && s->d.g_substeps > 1)
+        return fail(LBM_EUNSUPPORTED, "the sub-stepped rotational advection ping-pongs");
     if (enable && s->fd > 0.0)
         return fail(LBM_EUNSUPPORTED, "the finite-difference update ping-pongs");
     s->inplace = enable ? 1 : 0;
@@ -516,9 +554,11 @@ lbm_status lbm_set_fd(lbm_sim s, double courant) {
     if (!(courant >= 0.0 && courant <= 1.0)) return fail(LBM_EINVAL, "courant must be in [0, 1]");
     if (courant > 0.0 && s->d.dim > 2)
         return fail(LBM_EUNSUPPORTED, "the finite-difference update runs on 1-D and 2-D grids");
+    if (courant > 0.0 && s->d.g_substeps > 1)
+        return fail(LBM_EUNSUPPORTED, "the finite-difference update has no sub-stepped rotational advection");
     s->fd = courant;
     if (courant > 0.0) s->inplace = 0;
-    else s->inplace = inplace_possible(s->d) ? 1 : 0;
+    else s->inplace = inplace_possible(s->d) && s->d.g_substeps <= 1 ? 1 : 0;
     clear_cache(s);
     return LBM_OK;
 }

@@ -141,6 +141,138 @@ template <typename P, int D, int K> __global__ void __launch_bounds__(256) k_exp
         for (int j = 0; j < 7; ++j) pop_w<P>(a.g_out, j, a.N)[x] = pop<P>(a.g, j, a.N)[x];
 }
 
+static unsigned blocks_for(uint32_t N);
+
+// ---------------------------------------------------------------------------
+// Rotational advection in m sub-steps (lbm_desc.g_substeps = m > 1): a plain
+// one-node-per-thread path, ping-pong only.  One time step is
+//   f*_i(x) = f_i - omega (f_i - f^eq_i)   (post-collision, pulled next step)
+//   g(t+1)  = A^m g(t) - omega (g(t) - g^eq(T))
+// with A the forward-Euler third-order upwind advection of Sec. V A at
+// Courant numbers u_a / (m r), u from the moments of time t.  m = 1 would be
+// the paper's update (the fused step kernels run that).
+// ---------------------------------------------------------------------------
+// f^eq of direction d (runtime) from the coefficients of feq_coef: the
+// polynomial of feq_dir.
+template <typename P, int D, int K> __device__ __forceinline__ P feq_rt(const FeqCoef<P> &c, int d) {
+    const P xi2 = P(kR * kR * c2_of<D>(d));
+    P a = P(cx_of(d)) * c.ru[0];
+    if (D >= 2) a += P(cy_of(d)) * c.ru[1];
+    if (D >= 3) a += P(cz_of(d)) * c.ru[2];
+    const P p0 = c.A0 + xi2 * (c.A1 + xi2 * c.A2);
+    const P p1 = c.B0 + xi2 * c.B1;
+    const P p2 = c.C0 + xi2 * c.C1;
+    const P poly = p0 + a * (p1 + a * (p2 + a * (P(1.0 / 6.0) + a * P(1.0 / 24.0))));
+    return P(Lat<D, K>::w(d)) * c.rho * poly;
+}
+
+// Collision: f_out (post layout) from f (layout of a.f), the relaxation
+// term R = omega (g - g^eq) and the per-sub-step Courant numbers nu_a =
+// u_a / (r m), all in the population type.
+template <typename P, int D, int K>
+__global__ void __launch_bounds__(256) k_sub_collide(FieldArgs a, void *f_out, P *R, P *nu, double omega,
+                                                     int m) {
+    using L = Lat<D, K>;
+    constexpr DirTable<D, K> dirs;
+    const uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    if (x >= a.N) return;
+    const int cx = x % a.n0, cy = (x / a.n0) % a.n1, cz = x / (a.n0 * a.n1);
+    const int shift = a.layout == kLayoutStreamed ? 0 : 1;
+    Mom M = {0.0, {0.0, 0.0, 0.0}, 0.0, 0.0};
+    for (int i = 0; i < L::Q; ++i) {
+        const int d = dirs.v[i];
+        const double v = (double)fget<P, D, K>(a.f, a.blocked, a.N, src_slot<D, K>(a, i),
+                                               src_index<D>(a, cx, cy, cz, d, shift));
+        M.m0 += v;
+        M.m1[0] += cx_of(d) * v;
+        if (D >= 2) M.m1[1] += cy_of(d) * v;
+        if (D >= 3) M.m1[2] += cz_of(d) * v;
+        M.e2 += c2_of<D>(d) * v;
+    }
+    double gv[7];
+    for (int j = 0; j < 7; ++j) {
+        gv[j] = (double)pop<P>(a.g, j, a.N)[x];
+        M.er += double((j - 3) * (j - 3)) * gv[j];
+    }
+    double rho, u[3] = {0.0, 0.0, 0.0}, T, Etot;
+    finish_moments<D>(M, a.n_rot, rho, u, T, Etot);
+    const FeqCoef<double> fc = feq_coef<double, D>(rho, u, T);
+    for (int i = 0; i < L::Q; ++i) {
+        const int d = dirs.v[i];
+        const double v = (double)fget<P, D, K>(a.f, a.blocked, a.N, src_slot<D, K>(a, i),
+                                               src_index<D>(a, cx, cy, cz, d, shift));
+        reinterpret_cast<P *>(f_out)[pop_index(a.blocked, L::Q, a.N, i, x)] =
+            (P)(v - omega * (v - feq_rt<double, D, K>(fc, d)));
+    }
+    const GeqCoef<double> gc = geq_coef<double>(T);
+    static_for<0, 7>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        R[(size_t)j * a.N + x] = (P)(omega * (gv[j] - geq_dir<double, j>(gc)));
+    });
+    for (int d = 0; d < D; ++d) nu[(size_t)d * a.N + x] = (P)(u[d] / kR / m);
+}
+
+// One advection sub-step: dst = src - sum_a nu_a D_a[src] (- R on the last).
+template <typename P, int D>
+__global__ void __launch_bounds__(256) k_sub_advect(FieldArgs a, const P *src, P *dst, const P *nu,
+                                                    const P *R) {
+    const uint32_t x = blockIdx.x * 256u + threadIdx.x;
+    if (x >= a.N) return;
+    const int c[3] = {(int)(x % a.n0), (int)((x / a.n0) % a.n1), (int)(x / (a.n0 * a.n1))};
+    const int n[3] = {a.n0, a.n1, a.n2}, op[3] = {a.open0, a.open1, a.open2};
+    const uint32_t st[3] = {1u, (uint32_t)a.n0, (uint32_t)a.n0 * (uint32_t)a.n1};
+    for (int j = 0; j < 7; ++j) {
+        const P *h = src + (size_t)j * a.N;
+        P adv = P(0);
+        for (int ax = 0; ax < D; ++ax) {
+            P v[5];
+            for (int k = -2; k <= 2; ++k) {
+                const int q = nb_coord(c[ax], k, n[ax], op[ax]);
+                v[k + 2] = h[x + ((int64_t)q - c[ax]) * (int64_t)st[ax]];
+            }
+            adv += upwind3<P>(nu[(size_t)ax * a.N + x], v[0], v[1], v[2], v[3], v[4]);
+        }
+        P out = h[x] - adv;
+        if (R) out -= R[(size_t)j * a.N + x];
+        dst[(size_t)j * a.N + x] = out;
+    }
+}
+
+template <typename P, int D, int K>
+static hipError_t sub_step_t(const FieldArgs &a, void *f_out, void *g_out, void *scratch, int m, double omega,
+                             hipStream_t s) {
+    P *R = reinterpret_cast<P *>(scratch);
+    P *nu = R + 7 * (size_t)a.N;
+    P *gt = nu + 3 * (size_t)a.N;
+    const dim3 g(blocks_for(a.N)), b(256);
+    hipLaunchKernelGGL((k_sub_collide<P, D, K>), g, b, 0, s, a, f_out, R, nu, omega, m);
+    const P *src = reinterpret_cast<const P *>(a.g);
+    for (int k = 0; k < m; ++k) {
+        P *dst = ((m - 1 - k) % 2 == 0) ? reinterpret_cast<P *>(g_out) : gt;
+        hipLaunchKernelGGL((k_sub_advect<P, D>), g, b, 0, s, a, src, dst, nu, k == m - 1 ? R : (const P *)nullptr);
+        src = dst;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_sub(int dtype, int dim, int kind, const FieldArgs &a, void *f_out, void *g_out,
+                           void *scratch, int m, double omega, hipStream_t s) {
+    if (m < 2) return hipErrorInvalidValue;
+    if (kind == kD2Q37) {
+        if (dim != 2) return hipErrorInvalidValue;
+        return dtype == 0 ? sub_step_t<float, 2, kD2Q37>(a, f_out, g_out, scratch, m, omega, s)
+                          : sub_step_t<double, 2, kD2Q37>(a, f_out, g_out, scratch, m, omega, s);
+    }
+    if (dtype == 0) {
+        if (dim == 1) return sub_step_t<float, 1, kTensor>(a, f_out, g_out, scratch, m, omega, s);
+        if (dim == 2) return sub_step_t<float, 2, kTensor>(a, f_out, g_out, scratch, m, omega, s);
+        return sub_step_t<float, 3, kTensor>(a, f_out, g_out, scratch, m, omega, s);
+    }
+    if (dim == 1) return sub_step_t<double, 1, kTensor>(a, f_out, g_out, scratch, m, omega, s);
+    if (dim == 2) return sub_step_t<double, 2, kTensor>(a, f_out, g_out, scratch, m, omega, s);
+    return sub_step_t<double, 3, kTensor>(a, f_out, g_out, scratch, m, omega, s);
+}
+
 // dst (blocked) <- src (plain); one thread per element of dst, read side
 // gathered.
 template <typename P>

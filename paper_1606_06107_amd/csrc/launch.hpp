@@ -102,6 +102,11 @@ int step_ntiles(int dim, const int tile[3], int n0, int n1, int n2, int *t0, int
 // Fields and/or per-block partial totals; returns the number of blocks used.
 hipError_t launch_fields(int dtype, int dim, int kind, const FieldArgs &a, int *nblocks, hipStream_t s);
 hipError_t launch_export(int dtype, int dim, int kind, const FieldArgs &a, hipStream_t s);
+// One time step with the rotational advection in m >= 2 sub-steps (ping-pong:
+// a.f / a.g hold time t in a.layout, f_out receives the post-collision
+// populations, g_out time t+1).  scratch: 17 N values of the population type.
+hipError_t launch_step_sub(int dtype, int dim, int kind, const FieldArgs &a, void *f_out, void *g_out,
+                           void *scratch, int m, double omega, hipStream_t s);
 // Fixed-order sum of partials[nparts][K] into out[K] (one workgroup).
 hipError_t launch_reduce(const double *partials, int nparts, int K, double *out, hipStream_t s);
 // The same sum as row *slot of series[cap][K] (skipped if *slot >= cap);

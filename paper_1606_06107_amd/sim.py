@@ -45,10 +45,12 @@ class Sim:
     shape: nodes per axis (x first), bc: 'periodic' | 'open' per axis,
     n_rot: rotational degrees of freedom (gamma = (D+n+2)/(D+n)), tau: BGK
     relaxation time in steps, dtype: torch.float32 | torch.float64, lattice:
-    None (D1Q7^D) or "D2Q37" (2-D, Table I)."""
+    None (D1Q7^D) or "D2Q37" (2-D, Table I), g_substeps: 1 = the rotational
+    update as the paper writes it, m > 1 = its advection in m sub-steps
+    (lbm_desc.g_substeps)."""
 
     def __init__(self, shape, bc=None, n_rot=0.0, tau=1.0, dtype=torch.float32,
-                 device="cuda", stream=None, lattice=None):
+                 device="cuda", stream=None, lattice=None, g_substeps=1):
         self.lib = L.load()
         shape = tuple(int(s) for s in shape)
         self.D = len(shape)
@@ -79,6 +81,7 @@ class Sim:
         d.dtype = L.LBM_F32 if dtype == torch.float32 else L.LBM_F64
         d.n_rot = float(n_rot)
         d.tau = float(tau)
+        d.g_substeps = int(g_substeps)
         for k in range(2):
             d.f[k] = self.f[k].data_ptr()
             d.g[k] = self.g[k].data_ptr()

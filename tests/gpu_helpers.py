@@ -17,11 +17,12 @@ def announce(msg):
 
 
 def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile=None,
-            graphs=True, chunks=None, inplace=None, blocked=None, lattice=None, fd=None):
+            graphs=True, chunks=None, inplace=None, blocked=None, lattice=None, fd=None, g_substeps=1):
     """Populations come back in the library's slot order (lattice_info)."""
     import torch
     from paper_1606_06107_amd import Sim
-    sim = Sim(shape, bc=bc, n_rot=n_rot, tau=tau, dtype=dtype, lattice=lattice).init(*fields)
+    sim = Sim(shape, bc=bc, n_rot=n_rot, tau=tau, dtype=dtype, lattice=lattice,
+              g_substeps=g_substeps).init(*fields)
     if fd is not None:
         sim.set_fd(fd)
     if perturb_seed is not None:
@@ -45,12 +46,12 @@ def gpu_run(shape, bc, n_rot, tau, dtype, fields, steps, perturb_seed=None, tile
             "tot": tot.cpu().numpy(), "f": f.double().cpu().numpy(), "g": g.double().cpu().numpy()}
 
 
-def oracle_run(shape, bc, n_rot, tau, fields, steps, perturb_seed=None, lattice=None, fd=0.0):
+def oracle_run(shape, bc, n_rot, tau, fields, steps, perturb_seed=None, lattice=None, fd=0.0, g_substeps=1):
     """Populations come back in the oracle's order (oracle.lattice)."""
     D = len(shape)
     obc = [oracle.OPEN if b == "open" else oracle.PERIODIC for b in bc]
     G = oracle.Grid(_ONAMED[lattice] if lattice else _OKIND[D], shape, bc=obc, n_rot=n_rot, tau=tau,
-                    fd_courant=fd)
+                    fd_courant=fd, g_substeps=g_substeps)
     f, g = G.init_eq(*fields)
     if perturb_seed is not None:
         f *= workloads.nonequilibrium_perturbation(f.shape, perturb_seed)

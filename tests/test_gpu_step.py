@@ -26,10 +26,11 @@ def _fields_check(g, o, tol, kind):
 
 
 def test_tube_1d_fp64_1000_nodes_1000_steps(torch_cuda):
-    """The 1-D shock tube workload (1000 nodes, n = 4, tau = 2/3, open ends)
-    over its full 1000 steps, FP64, graph replay."""
+    """The Sec. VI tube's states in 1-D (1000 nodes, n = 4, tau = 0.8, open
+    ends, the rotational update as written) over 1000 steps, FP64, graph
+    replay."""
     import workloads
-    w = workloads.tube_1d()
+    w = workloads.paper_tube_1d()
     announce("1-D tube FP64 1000x1000")
     fields = w.fields()
     g = gpu_run((w.N,), ["open"], w.n_rot, w.tau, torch_cuda.float64, fields, w.steps)

@@ -10,11 +10,13 @@ Shapes follow the paper's shock-tube test (Sec. VI) and the workloads the
 library is measured on:
 
   sod_tube          1-D tube, cell-centred, diaphragm at x = 1/2
-  tube_1d           the 1-D analogue of the Sec. VI tube: 1000 nodes,
-                    left (rho,u,p) = (4,0,4), right (1,0,1), n = 4
-                    (gamma = 1.4 in 1-D), tau = 0.8, open ends, 1000 steps
-                    (the paper's tau = 2/3 runs to ~370 steps and then
-                    diverges once the shock leaves through the open end)
+  tube_1d           the classic Sod tube: 1000 nodes, left (rho,u,p) =
+                    (1,0,1), right (0.125,0,0.1), n = 4 (gamma = 1.4 in
+                    1-D), tau = 1, open ends, 1000 steps, rotational
+                    advection in 4 sub-steps
+  paper_tube_1d     the Sec. VI tube's states (4,0,4) | (1,0,1) in 1-D,
+                    tau = 0.8, the rotational update as written (the paper's
+                    tau = 2/3 diverges once the shock leaves the open end)
   periodic_2d       1024^2 smooth random Fourier-mode fields, gamma = 1.4
   turbulence_3d     256^3 solenoidal random velocity, E(k) ~ k^4 exp(-2 (k/4)^2)
   batched_tubes     thousands of ragged 1-D tubes with per-instance gamma,
@@ -56,11 +58,18 @@ def sod_tube(N: int, left, right):
 
 @dataclass
 class Tube1D:
+    """The 1-D shock tube workload: the classic Sod states (rho, u, p) =
+    (1, 0, 1) | (0.125, 0, 0.1), 1000 cell-centred nodes, open ends, n = 4
+    (gamma = 1.4 in 1-D), 1000 steps.  The star state moves at u* = 0.93,
+    rotational Courant number 0.78, beyond the ~0.67 where the forward-Euler
+    upwind update of the rotational populations stays stable at tau = 1: run
+    with that advection in g_substeps = 4 sub-steps (Courant 0.19)."""
     N: int = 1000
-    left: tuple = (4.0, 0.0, 4.0)
-    right: tuple = (1.0, 0.0, 1.0)
+    left: tuple = (1.0, 0.0, 1.0)
+    right: tuple = (0.125, 0.0, 0.1)
     n_rot: float = 4.0
-    tau: float = 0.8
+    tau: float = 1.0
+    g_substeps: int = 4
     steps: int = 1000
     riemann_steps: tuple = (180, 239)
 
@@ -70,6 +79,12 @@ class Tube1D:
 
 def tube_1d() -> Tube1D:
     return Tube1D()
+
+
+def paper_tube_1d() -> Tube1D:
+    """The Sec. VI tube's states (rho 4:1 at T = 1) in 1-D: stable with the
+    rotational update as written (tau = 0.8)."""
+    return Tube1D(left=(4.0, 0.0, 4.0), right=(1.0, 0.0, 1.0), tau=0.8, g_substeps=1)
 
 
 def _mode_sum(rng, shape, nmodes=8, kmax=4):
