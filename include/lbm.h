@@ -362,9 +362,10 @@ lbm_status lbm_sur_pack(const lbm_sur_desc *desc, void *hip_stream);
 
 /* Inference: x [3][B][L] FP64 fields (rho, u, T), gamma [B] FP64 ->
  * y [3][B][L] FP64 predicted fields LBM_SUR_K steps later.  y may not
- * alias x. */
+ * alias x.  active: NULL, or device int32 [B]: tubes with active[b] == 0
+ * are skipped (their rows of y are not written). */
 lbm_status lbm_sur_forward(const lbm_sur_desc *desc, const double *x, const double *gamma,
-                           double *y, void *hip_stream);
+                           const int32_t *active, double *y, void *hip_stream);
 
 /* Training step: forward on x, loss = mean over nodes and channels of
  * (Y_c - (target_c - x_c) / 0.1)^2, backward.  grads [LBM_SUR_NPARAMS] FP32

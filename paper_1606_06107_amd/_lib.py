@@ -71,7 +71,7 @@ SIGNATURES = {
     "lbm_sur_bf16_bytes": (c_sz, []),
     "lbm_sur_workspace_bytes": (c_sz, [ctypes.POINTER(LbmSurDesc)]),
     "lbm_sur_pack": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp]),
-    "lbm_sur_forward": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp]),
+    "lbm_sur_forward": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbm_sur_backward": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lbm_sur_adam": (c_i32, [ctypes.POINTER(LbmSurDesc), c_vp, c_vp, c_vp, c_vp, ctypes.c_float,
                              ctypes.c_float, ctypes.c_float, ctypes.c_float, c_i64, c_vp]),

@@ -465,6 +465,7 @@ constexpr int HS = C + 4;               // FP32 row stride in LDS
 struct FwdArgs {
     int B, L, T, ntile;
     const double *x, *gamma;
+    const int32_t *active;  // NULL, or [B]: tubes with active[b] == 0 are skipped
     const float *P;
     const __bf16 *Q;
     double *y;
@@ -501,6 +502,7 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
     for (int e = threadIdx.x; e < 4 * HS; e += 64 * FNW) Hs[e < 2 * HS ? e : (FR + 2) * HS + e - 2 * HS] = 0.0f;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, n32 = l & 31, hl = l >> 5;
     const int b = blockIdx.x / a.ntile, tile = blockIdx.x % a.ntile;
+    if (a.active && !a.active[b]) return;  // workgroup-uniform
     const int t0 = tile * FOUTR - FHALO;  // token of row 0
     const int r0 = 32 * w;
     const size_t BL = (size_t)a.B * a.L;
@@ -889,8 +891,8 @@ lbm_status lbm_sur_pack(const lbm_sur_desc *d, void *stream) {
     return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));
 }
 
-lbm_status lbm_sur_forward(const lbm_sur_desc *d, const double *x, const double *gamma, double *y,
-                           void *stream) {
+lbm_status lbm_sur_forward(const lbm_sur_desc *d, const double *x, const double *gamma,
+                           const int32_t *active, double *y, void *stream) {
     lbm_status st = svalidate(d);
     if (st) return st;
     if (!d->params || !d->params_bf16 || !d->workspace || !x || !gamma || !y)
@@ -898,7 +900,7 @@ lbm_status lbm_sur_forward(const lbm_sur_desc *d, const double *x, const double 
     if (x == y) return sfail(LBM_EINVAL, "y may not alias x");
     hipStream_t s = (hipStream_t)stream;
     const int T = d->length / PATCH, ntile = (T + FOUTR - 1) / FOUTR;
-    FwdArgs fa{d->batch, d->length, T, ntile, x, gamma, d->params, (const __bf16 *)d->params_bf16, y};
+    FwdArgs fa{d->batch, d->length, T, ntile, x, gamma, active, d->params, (const __bf16 *)d->params_bf16, y};
     hipLaunchKernelGGL(k_fwd_fused, dim3((unsigned)(d->batch * ntile)), dim3(64 * FNW), 0, s, fa);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LBM_OK : sfail(LBM_ELAUNCH, hipGetErrorString(e));

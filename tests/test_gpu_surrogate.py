@@ -375,3 +375,20 @@ def test_rollout_plain_first_then_all_accepted(torch_cuda):
     for _ in range(calls - 1):
         ref = sur.forward(ref, gd)
     assert np.array_equal(xr.cpu().numpy(), ref.cpu().numpy())
+
+
+def test_forward_active_mask(torch_cuda):
+    """Tubes with active[b] == 0 are skipped: their rows of y keep what was
+    there, the others are bitwise those of the unmasked launch."""
+    announce("surrogate forward active mask")
+    import torch
+    B, L = 3, 512
+    p, x, gamma, _ = _problem(seed=5, B=B, L=L)
+    sur = _gpu(torch, p, B, L)
+    xd, gd = _dev(torch, x), _dev(torch, gamma)
+    full = sur.forward(xd, gd).cpu().numpy()
+    y = torch.full_like(xd, 7.0)
+    active = torch.tensor([1, 0, 1], dtype=torch.int32, device="cuda")
+    got = sur.forward(xd, gd, y, active=active).cpu().numpy()
+    assert np.array_equal(got[:, [0, 2]], full[:, [0, 2]])
+    assert np.all(got[:, 1] == 7.0)
