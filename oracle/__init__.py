@@ -27,6 +27,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# LBMX_ORACLE_LIB names another build of the same source (the sanitizer
+# build of the test suite's address/undefined-behaviour check).
+_LIB_LOAD = os.environ.get("LBMX_ORACLE_LIB") or _LIB
 
 D1Q7, D2Q49, D3Q343, D2Q37 = 1, 2, 3, 4
 PERIODIC, OPEN = 0, 1
@@ -64,9 +67,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _LIB_LOAD == _LIB and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LIB_LOAD)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         L.orc_d1q7_r.restype = ctypes.c_double

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbmx.so")
+# LBMX_LIB names another build of the same sources (the host-sanitizer build
+# of the test suite's address/undefined-behaviour check).
+LIB_PATH = os.environ.get("LBMX_LIB") or os.path.join(HERE, "liblbmx.so")
 
 LBM_ABI_VERSION = 2
 LBM_OK, LBM_EINVAL, LBM_EDEVICE, LBM_ENOMEM, LBM_EUNSUPPORTED, LBM_ELAUNCH = range(6)

@@ -770,13 +770,15 @@ lbm_status sfail(lbm_status s, const std::string &m) {
     return s;
 }
 
+// Carves 256-byte aligned pieces out of the workspace.  With no workspace
+// (sizing only) the pieces are offsets from address 0, formed as integers.
 struct WS {
     size_t off = 0;
-    char *base;
-    explicit WS(void *b) : base((char *)b) {}
+    uintptr_t base;
+    explicit WS(void *b) : base((uintptr_t)b) {}
     template <typename T> T *take(size_t n) {
         off = (off + 255) / 256 * 256;
-        T *p = (T *)(base + off);
+        T *p = reinterpret_cast<T *>(base + off);
         off += n * sizeof(T);
         return p;
     }
