@@ -164,6 +164,15 @@ lbm_status lbm_set_monitor(lbm_sim sim, int64_t every, double *series, int64_t c
 /* Time-step counter since lbm_init. */
 lbm_status lbm_time(lbm_sim sim, int64_t *t);
 
+/* Debug flags.  LBM_DEBUG_POISON: before every step, fill the buffers the
+ * step writes without reading them (the rotational destination; with
+ * ping-pong streaming the translational one too) with quiet NaN, so that a
+ * population the step fails to write shows up as NaN in the next step's
+ * fields.  Same results otherwise; one extra fill per step.  0 turns them off.
+ * Errors: LBM_EINVAL. */
+enum { LBM_DEBUG_POISON = 1 };
+lbm_status lbm_set_debug(lbm_sim sim, int32_t flags);
+
 /* Enable (1) or disable (0) HIP-graph replay of multi-step calls. */
 lbm_status lbm_set_graphs(lbm_sim sim, int32_t enable);
 

@@ -18,6 +18,7 @@ LBM_OK, LBM_EINVAL, LBM_EDEVICE, LBM_ENOMEM, LBM_EUNSUPPORTED, LBM_ELAUNCH = ran
 LBM_D1Q7, LBM_D2Q49, LBM_D3Q343, LBM_D2Q37 = 1, 2, 3, 4
 LBM_F32, LBM_F64 = 0, 1
 LBM_BC_PERIODIC, LBM_BC_OPEN = 0, 1
+LBM_DEBUG_POISON = 1
 
 c_i32, c_i64, c_dbl, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -56,6 +57,7 @@ SIGNATURES = {
     "lbm_set_monitor": (c_i32, [c_vp, c_i64, c_vp, c_i64]),
     "lbm_time": (c_i32, [c_vp, ctypes.POINTER(c_i64)]),
     "lbm_set_graphs": (c_i32, [c_vp, c_i32]),
+    "lbm_set_debug": (c_i32, [c_vp, c_i32]),
     "lbm_set_tile": (c_i32, [c_vp, c_i32, c_i32, c_i32]),
     "lbm_set_inplace": (c_i32, [c_vp, c_i32]),
     "lbm_set_blocked": (c_i32, [c_vp, c_i32]),

@@ -153,9 +153,10 @@ struct lbm_sim_s {
     int64_t mon_every = 0;
     double *mon_series = nullptr;
     int64_t mon_cap = 0;
+    int debug = 0;                        // lbm_set_debug flags
     struct Entry {
         int64_t n, t0, every, cap;
-        int fcur, gcur, layout, inplace, tile0, tile1;
+        int fcur, gcur, layout, inplace, tile0, tile1, debug;
         double *series;
         hipGraphExec_t exec;
     };
@@ -244,8 +245,23 @@ hipError_t enqueue_step_sub(lbm_sim s, hipStream_t st) {
     return hipSuccess;
 }
 
+// Debug poisoning (LBM_DEBUG_POISON): quiet NaN into the buffers the next
+// step writes without reading (the ping-pong destinations), so a value the
+// step fails to write shows up as NaN.
+hipError_t poison_destinations(lbm_sim s, hipStream_t st) {
+    const lbm_desc &d = s->d;
+    const size_t N = (size_t)N_of(d);
+    hipError_t e = lbmx::launch_fill_nan(d.dtype, d.g[s->gcur ^ 1], 7 * N, st);
+    if (e == hipSuccess && !s->inplace) e = lbmx::launch_fill_nan(d.dtype, d.f[s->fcur ^ 1], (size_t)q_of(d.lattice) * N, st);
+    return e;
+}
+
 // Enqueue one time step on stream st and advance the host-side state.
 hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
+    if (s->debug & LBM_DEBUG_POISON) {
+        const hipError_t e = poison_destinations(s, st);
+        if (e != hipSuccess) return e;
+    }
     if (s->fd > 0.0) return enqueue_step_fd(s, st);
     if (s->d.g_substeps > 1) return enqueue_step_sub(s, st);
     const lbm_desc &d = s->d;
@@ -350,7 +366,7 @@ lbm_status graph_for(lbm_sim s, int64_t nsteps, hipGraphExec_t *out) {
         if (en.n == nsteps && en.fcur == s->fcur && en.gcur == s->gcur && en.layout == s->layout &&
             en.inplace == s->inplace && en.t0 == t0key && en.tile0 == s->tile[0] &&
             en.tile1 == s->tile[1] && en.every == s->mon_every && en.cap == s->mon_cap &&
-            en.series == s->mon_series) {
+            en.series == s->mon_series && en.debug == s->debug) {
             *out = en.exec;
             return LBM_OK;
         }
@@ -379,7 +395,7 @@ lbm_status graph_for(lbm_sim s, int64_t nsteps, hipGraphExec_t *out) {
         s->cache.erase(s->cache.begin());
     }
     s->cache.push_back({nsteps, t0key, s->mon_every, s->mon_cap, fcur0, gcur0, lay0, s->inplace,
-                        s->tile[0], s->tile[1], s->mon_series, exec});
+                        s->tile[0], s->tile[1], s->debug, s->mon_series, exec});
     *out = exec;
     return LBM_OK;
 }
@@ -523,6 +539,13 @@ lbm_status lbm_set_monitor(lbm_sim s, int64_t every, double *series, int64_t cap
 lbm_status lbm_time(lbm_sim s, int64_t *t) {
     if (!s || !t) return fail(LBM_EINVAL, "NULL argument");
     *t = s->t;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_debug(lbm_sim s, int32_t flags) {
+    if (!s) return fail(LBM_EINVAL, "sim is NULL");
+    if (flags & ~LBM_DEBUG_POISON) return fail(LBM_EINVAL, "unknown debug flags 0x%x", flags);
+    s->debug = flags;
     return LBM_OK;
 }
 

@@ -320,6 +320,19 @@ __global__ void __launch_bounds__(256) k_reduce(const double *partials, int npar
     }
 }
 
+// Quiet NaN into n values (debug poisoning of a step's destination).
+template <typename P> __global__ void __launch_bounds__(256) k_fill_nan(P *p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = __builtin_nan("");
+}
+
+hipError_t launch_fill_nan(int dtype, void *p, size_t n, hipStream_t s) {
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    if (dtype == 0) hipLaunchKernelGGL(k_fill_nan<float>, g, b, 0, s, (float *)p, n);
+    else hipLaunchKernelGGL(k_fill_nan<double>, g, b, 0, s, (double *)p, n);
+    return hipGetLastError();
+}
+
 __global__ void k_set_i64(int64_t *p, int64_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }

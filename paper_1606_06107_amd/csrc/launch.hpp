@@ -113,6 +113,8 @@ hipError_t launch_reduce(const double *partials, int nparts, int K, double *out,
 // *slot then advances by one (device int64).
 hipError_t launch_reduce_series(const double *partials, int nparts, int K, double *series, int64_t cap,
                                 int64_t *slot, hipStream_t s);
+// Quiet NaN into n values of dtype (a kernel: may be part of a graph).
+hipError_t launch_fill_nan(int dtype, void *p, size_t n, hipStream_t s);
 // *p = v on the stream (a kernel, so the write may be part of a graph).
 hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);
 

@@ -97,6 +97,7 @@ class Sim:
         self._inplace = None
         self._blocked = None
         self._fd = None
+        self._debug = None
 
     def _apply_settings(self):
         if self._fd is not None:  # first: it decides the streaming scheme
@@ -109,6 +110,8 @@ class Sim:
             L.check(self.lib.lbm_set_graphs(self.handle, 1 if self._graphs else 0))
         if self._inplace is not None:
             L.check(self.lib.lbm_set_inplace(self.handle, 1 if self._inplace else 0))
+        if self._debug is not None:
+            L.check(self.lib.lbm_set_debug(self.handle, L.LBM_DEBUG_POISON if self._debug else 0))
 
     def _stream_ptr(self):
         return ctypes.c_void_p(self.stream.cuda_stream)
@@ -154,6 +157,13 @@ class Sim:
         current state without running it (host work done ahead of a timed
         or latency-critical call)."""
         L.check(self.lib.lbm_prepare(self.handle, int(nsteps)))
+        return self
+
+    def set_debug(self, poison: bool):
+        """Poison every step's write-only destinations with NaN first, so that
+        a value a step fails to write shows up (lbm_set_debug)."""
+        L.check(self.lib.lbm_set_debug(self.handle, L.LBM_DEBUG_POISON if poison else 0))
+        self._debug = bool(poison)
         return self
 
     def set_graphs(self, on: bool):

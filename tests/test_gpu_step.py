@@ -433,3 +433,33 @@ def test_stream_copy(torch_cuda):
                                    src.numel() * 4, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
+
+
+@pytest.mark.parametrize("case", ["2d-pingpong", "2d-inplace", "3d-blocked", "1d-fd", "2d-substeps", "d2q37"])
+def test_nan_poison_debug_mode(torch_cuda, case):
+    """With every step's write-only destinations poisoned with NaN first
+    (lbm_set_debug), the state after several steps is bitwise the one
+    without: every step writes every value it is responsible for."""
+    import torch
+    from paper_1606_06107_amd import Sim
+    shape, bc, kw, fd = {"2d-pingpong": ((70, 30), ["periodic", "open"], {}, None),
+                         "2d-inplace": ((70, 30), ["periodic", "periodic"], {}, None),
+                         "3d-blocked": ((64, 6, 5), ["periodic"] * 3, {}, None),
+                         "1d-fd": ((90,), ["open"], {}, 0.2),
+                         "2d-substeps": ((40, 24), ["open", "periodic"], {"g_substeps": 3}, None),
+                         "d2q37": ((70, 30), ["periodic", "open"], {"lattice": "D2Q37"}, None)}[case]
+    fields = smooth_fields(shape, 15)
+    announce(f"NaN poison {case}")
+    out = []
+    for poison in (False, True):
+        sim = Sim(shape, bc=bc, n_rot=2.0, tau=0.8, dtype=torch.float32, **kw).init(*fields)
+        if fd:
+            sim.set_fd(fd)
+        sim.set_debug(poison)
+        sim.step(7)
+        sim.step(1)
+        f, g = sim.populations()
+        torch.cuda.synchronize()
+        out.append((f.cpu().numpy(), g.cpu().numpy()))
+    assert np.isfinite(out[1][0]).all() and np.isfinite(out[1][1]).all()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
