@@ -276,7 +276,13 @@ typedef struct {
     int32_t block;          /* threads per workgroup: 256, 512 or 1024 (0 = default) */
     int32_t chunk;          /* nodes per on-chip chunk, 0 = largest that fits */
     int32_t superstep;      /* time steps per on-chip pass of a chunked tube
-                               (0 = default 24) */
+                               (0 = default 24, fewer if the halo of the
+                               sub-steps below does not leave room) */
+    int32_t g_substeps;     /* as lbm_desc.g_substeps, for every tube: 0 or 1 =
+                               the rotational update as written; m in [2, 64]
+                               = its advection in m sub-steps of Courant number
+                               u / (m r), the relaxation once per step (chunk
+                               halos grow to max(3, 2m) nodes per step) */
 } lbm_batch_desc;
 
 size_t lbm_batch_workspace_bytes(const lbm_batch_desc *desc);

@@ -34,7 +34,8 @@ class LbmBatchDesc(ctypes.Structure):
                 ("total_nodes", c_i64), ("offsets", c_vp), ("n_rot", c_vp), ("tau", c_vp),
                 ("nsteps", c_vp), ("f", c_vp * 2), ("g", c_vp * 2), ("status", c_vp),
                 ("steps_done", c_vp),
-                ("workspace", c_vp), ("block", c_i32), ("chunk", c_i32), ("superstep", c_i32)]
+                ("workspace", c_vp), ("block", c_i32), ("chunk", c_i32), ("superstep", c_i32),
+                ("g_substeps", c_i32)]
 
 
 class LbmSurDesc(ctypes.Structure):

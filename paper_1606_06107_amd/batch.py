@@ -19,10 +19,11 @@ def _p(t):
 class Batch:
     """lengths[I] (>= 1 each), n_rot[I], tau[I], nsteps[I] (per call of
     step()).  block/chunk/superstep: launch shape (0 = library default;
-    chosen by the autotuner)."""
+    chosen by the autotuner).  g_substeps: rotational advection sub-steps
+    per step (1 = the update as written; lbm_batch_desc.g_substeps)."""
 
     def __init__(self, lengths, n_rot, tau, nsteps, dtype=torch.float32, device="cuda",
-                 block=0, chunk=0, superstep=0, stream=None):
+                 block=0, chunk=0, superstep=0, stream=None, g_substeps=1):
         self.lib = L.load()
         dev = torch.device(device)
         lengths = np.asarray(lengths, dtype=np.int64)
@@ -54,6 +55,7 @@ class Batch:
         d.status = self.status.data_ptr()
         d.steps_done = self.steps_done.data_ptr()
         d.block, d.chunk, d.superstep = int(block), int(chunk), int(superstep)
+        d.g_substeps = int(g_substeps)
         nbytes = self.lib.lbm_batch_workspace_bytes(ctypes.byref(d))
         self.workspace = torch.empty(max(nbytes, 256) // 4 + 64, dtype=torch.int32, device=dev)
         d.workspace = self.workspace.data_ptr()

@@ -64,6 +64,8 @@ struct BatchArgs {
     uint32_t total;
     int chunk;      // nodes per LDS buffer
     int superstep;  // steps per pass of a chunked tube
+    int m;          // rotational advection sub-steps per step (1: the update as written)
+    int hw;         // halo nodes a step reaches: max(3, 2 m)
 };
 
 // counter[]: on-chip tube queue head, chunk queue head and tail, on-chip and
@@ -129,7 +131,7 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
     __shared__ int s_cnt[2];
     __shared__ int part[1024];
     const int n = a.num;
-    const int inner = a.chunk - 6 * a.superstep;
+    const int inner = a.chunk - 2 * a.hw * a.superstep;
     if (threadIdx.x == 0) {
         a.counter[kCtrQueue] = 0;
         a.counter[kCtrHead] = 0;
@@ -265,10 +267,12 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
 // edges).  F, G: [7][C] arrays; shift = 0 if F holds streamed populations,
 // 1 if post-collision ones (gathered from x - c).
 // ---------------------------------------------------------------------------
-template <typename P>
+// ADV = false (sub-stepped rotational advection): go receives the
+// relaxation increment rl instead of g - adv + rl, *nu_out the Courant number.
+template <typename P, bool ADV = true>
 __device__ __forceinline__ void lds_node(const P *F, const P *G, int C, int x, int R, int shift,
                                          P om, double omega, double n_rot, P (&fo)[7], P (&go)[7],
-                                         double &rho, double &T) {
+                                         double &rho, double &T, P *nu_out = nullptr) {
     P fv[7], gv[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
@@ -330,7 +334,8 @@ __device__ __forceinline__ void lds_node(const P *F, const P *G, int C, int x, i
     P adv[7], rl[7];
     static_for<0, 7>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        adv[j] = upwind3<P>(nu, G[j * C + xm2], G[j * C + xm1], gv[j], G[j * C + xp1], G[j * C + xp2]);
+        if constexpr (ADV)
+            adv[j] = upwind3<P>(nu, G[j * C + xm2], G[j * C + xm1], gv[j], G[j * C + xp1], G[j * C + xp2]);
         rl[j] = om * (geq_dir<P, j>(gc) - gv[j]);
     });
     if constexpr (sizeof(P) == 4) {
@@ -347,8 +352,14 @@ __device__ __forceinline__ void lds_node(const P *F, const P *G, int C, int x, i
         for (int j = 0; j < 7; ++j)
             rl[j] += P(kW1[iabs(j - 3)]) * ((P)al + P((j - 3) * (j - 3)) * (P)ga);
     }
+    if constexpr (ADV) {
 #pragma unroll
-    for (int j = 0; j < 7; ++j) go[j] = gv[j] - adv[j] + rl[j];
+        for (int j = 0; j < 7; ++j) go[j] = gv[j] - adv[j] + rl[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) go[j] = rl[j];
+        *nu_out = nu;
+    }
 }
 
 // 0 healthy, 1 non-finite, 2 rho <= 0 or T <= 0.
@@ -367,9 +378,83 @@ __device__ __forceinline__ int health(double rho, double T) {
 // barrier of step s + 1 and so has read the flag of step s -- all threads
 // leave at the same step.  Returns the buffer index holding the result;
 // *shift_out its representation.
+// The rotational advection in m > 1 sub-steps (BatchArgs::m): per step, the
+// collision of every node (f to the other buffer, the rotational relaxation
+// increment and Courant number kept in registers, NPT nodes per thread),
+// then m advection passes over G with Courant number nu / m, one barrier
+// each, the last adding the relaxation increment.  g(t+1) = A^m g(t) + rl.
+// The translational and rotational buffers then alternate independently:
+// *gcur_out receives the index of the buffer holding g.
 template <typename P, int B>
+__device__ int lds_run_sub(P *F, P *G, int C, int R, int steps, int shift, P om, double omega,
+                           double n_rot, int m, int vlo, int vhi, int *bad, int *shift_out, int *ran,
+                           int *gcur_out) {
+    constexpr int NPT = (1536 + B - 1) / B;  // nodes per thread: C <= 1536
+    int cur = 0, gc = 0;
+    *ran = 0;
+    const P minv = P(1) / P(m);
+    for (int s = 0; s < steps; ++s) {
+        const P *Fi = F + cur * 7 * C;
+        P *Fo = F + (cur ^ 1) * 7 * C;
+        P rl[NPT][7], nu[NPT];
+        int h = 0;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int x = (int)threadIdx.x + k * B;
+            if (x < R) {
+                P fo[7];
+                double rho, T;
+                lds_node<P, false>(Fi, G + gc * 7 * C, C, x, R, shift, om, omega, n_rot, fo, rl[k], rho, T, &nu[k]);
+                nu[k] *= minv;
+#pragma unroll
+                for (int i = 0; i < 7; ++i) Fo[i * C + x] = fo[i];
+                if (x >= vlo && x < vhi) {
+                    const int hh = health(rho, T);
+                    h = hh > h ? hh : h;
+                }
+            }
+        }
+        for (int q = 0; q < m; ++q) {
+            const P *Gs = G + (gc ^ (q & 1)) * 7 * C;
+            P *Gd = G + (gc ^ ((q & 1) ^ 1)) * 7 * C;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int x = (int)threadIdx.x + k * B;
+                if (x < R) {
+                    const int xm2 = x - 2 < 0 ? 0 : x - 2, xm1 = x - 1 < 0 ? 0 : x - 1;
+                    const int xp1 = x + 1 >= R ? R - 1 : x + 1, xp2 = x + 2 >= R ? R - 1 : x + 2;
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) {
+                        const P *gj = Gs + j * C;
+                        P v = gj[x] - upwind3<P>(nu[k], gj[xm2], gj[xm1], gj[x], gj[xp1], gj[xp2]);
+                        if (q == m - 1) v += rl[k][j];
+                        Gd[j * C + x] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (h) atomicMax(&bad[s & 1], h);
+        shift = 1;
+        cur ^= 1;
+        gc ^= m & 1;
+        *ran = s + 1;
+        __syncthreads();
+        if (bad[s & 1]) break;
+    }
+    *shift_out = shift;
+    *gcur_out = gc;
+    return cur;
+}
+
+// SUB: the kernel variant for m > 1 (a separate instantiation, so that the
+// register allocation of the update as written does not change).
+template <typename P, int B, bool SUB>
 __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, double omega,
-                       double n_rot, int vlo, int vhi, int *bad, int *shift_out, int *ran) {
+                       double n_rot, int m, int vlo, int vhi, int *bad, int *shift_out, int *ran, int *gcur_out) {
+    if constexpr (SUB)
+        return lds_run_sub<P, B>(F, G, C, R, steps, shift, om, omega, n_rot, m, vlo, vhi, bad, shift_out, ran,
+                                 gcur_out);
     int cur = 0;
     *ran = 0;
     for (int s = 0; s < steps; ++s) {
@@ -398,6 +483,7 @@ __device__ int lds_run(P *F, P *G, int C, int R, int steps, int shift, P om, dou
         if (bad[s & 1]) break;
     }
     *shift_out = shift;
+    *gcur_out = cur;
     return cur;
 }
 
@@ -497,17 +583,19 @@ __device__ __forceinline__ void load_region(P *F, P *G, int C, const P *fs, cons
 // nodes per side read from (fs, gs), advanced sp steps in LDS, the interior
 // written to (fd, gd).  Returns the steps completed (sp unless a node of the
 // interior failed the health check, *bad then holds its kind).
-template <typename P, int B>
+template <typename P, int B, bool SUB>
 __device__ int run_chunk(P *F, P *G, int C, const P *fs, const P *gs, P *fd, P *gd, uint32_t tot, int64_t base,
-                         int L, int c0, int c1, int sp, P om, double omega, double n_rot, int *bad) {
-    const int halo = 3 * sp;
+                         int L, int c0, int c1, int sp, P om, double omega, double n_rot, int m, int hw,
+                         int *bad) {
+    const int halo = hw * sp;
     const int lo = c0 - halo > 0 ? c0 - halo : 0;
     const int hi = c1 + halo < L ? c1 + halo : L;
     const int R = hi - lo;
     load_region<P, B>(F, G, C, fs, gs, tot, base + lo, R);
-    int shift, ran;
-    const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo, bad, &shift, &ran);
-    const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+    int shift, ran, gcur;
+    const int cur = lds_run<P, B, SUB>(F, G, C, R, sp, 0, om, omega, n_rot, m, c0 - lo, c1 - lo, bad, &shift,
+                                       &ran, &gcur);
+    const P *Fr = F + cur * 7 * C, *Gr = G + gcur * 7 * C;
     const int W = c1 - c0;
     for (int e = threadIdx.x; e < 7 * W; e += B) {
         const int i = e / W, x = (c0 - lo) + (e - i * W);
@@ -523,7 +611,7 @@ __device__ int run_chunk(P *F, P *G, int C, const P *fs, const P *gs, P *fd, P *
 // One tube of the on-chip queue (queue position `item`): its whole time loop
 // on chip, or, in index-order mode, its passes chunk by chunk on this
 // workgroup.  Writes its status and steps.  s_bad: LDS flags, zero on entry.
-template <typename P, int B>
+template <typename P, int B, bool SUB>
 __device__ void whole_tube(const BatchArgs &a, int item, P *F, P *G, int C, int *s_bad) {
     const uint32_t tot = a.total;
     const int t = a.order[item];
@@ -547,11 +635,11 @@ __device__ void whole_tube(const BatchArgs &a, int item, P *F, P *G, int C, int 
     if (L <= C) {
         // whole tube on chip
         load_region<P, B>(F, G, C, f0, g0, tot, base, L);
-        int shift, ran;
-        const int cur = lds_run<P, B>(F, G, C, L, (int)steps, 0, om, omega, n_rot, 0, L, s_bad, &shift,
-                                      &ran);
+        int shift, ran, gcur;
+        const int cur = lds_run<P, B, SUB>(F, G, C, L, (int)steps, 0, om, omega, n_rot, a.m, 0, L, s_bad, &shift,
+                                           &ran, &gcur);
         done_total = ran;
-        const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+        const P *Fr = F + cur * 7 * C, *Gr = G + gcur * 7 * C;
         P *f0w = reinterpret_cast<P *>(a.f[0]);
         P *g0w = reinterpret_cast<P *>(a.g[0]);
         // back to streamed form: f(x) = f*(clamp(x - c))
@@ -575,7 +663,7 @@ __device__ void whole_tube(const BatchArgs &a, int item, P *F, P *G, int C, int 
             const P *gs = reinterpret_cast<const P *>(a.g[p & 1]);
             P *fd = reinterpret_cast<P *>(a.f[(p + 1) & 1]);
             P *gd = reinterpret_cast<P *>(a.g[(p + 1) & 1]);
-            const int halo = 3 * sp;
+            const int halo = a.hw * sp;
             const int inner = C - 2 * halo;  // > 0 by the host's choice of superstep
             int pass_ran = sp;
             for (int c0 = 0; c0 < L; c0 += inner) {
@@ -584,11 +672,11 @@ __device__ void whole_tube(const BatchArgs &a, int item, P *F, P *G, int C, int 
                 const int hi = c1 + halo < L ? c1 + halo : L;
                 const int R = hi - lo;
                 load_region<P, B>(F, G, C, fs, gs, tot, base + lo, R);
-                int shift, ran;
-                const int cur = lds_run<P, B>(F, G, C, R, sp, 0, om, omega, n_rot, c0 - lo, c1 - lo,
-                                              s_bad, &shift, &ran);
+                int shift, ran, gcur;
+                const int cur = lds_run<P, B, SUB>(F, G, C, R, sp, 0, om, omega, n_rot, a.m, c0 - lo, c1 - lo,
+                                                   s_bad, &shift, &ran, &gcur);
                 pass_ran = ran < pass_ran ? ran : pass_ran;
-                const P *Fr = F + cur * 7 * C, *Gr = G + cur * 7 * C;
+                const P *Fr = F + cur * 7 * C, *Gr = G + gcur * 7 * C;
                 const int W = c1 - c0;
                 for (int e = threadIdx.x; e < 7 * W; e += B) {
                     const int i = e / W, x = (c0 - lo) + (e - i * W);
@@ -612,7 +700,7 @@ __device__ void whole_tube(const BatchArgs &a, int item, P *F, P *G, int C, int 
     __syncthreads();
 }
 
-template <typename P, int B>
+template <typename P, int B, bool SUB>
 __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int C = a.chunk;
@@ -625,7 +713,7 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
     // Phase 1: chunks of the long tubes from the queue; on-chip tubes while
     // the queue is empty.  Phase 2: the remaining on-chip tubes.
     const int nlong = a.counter[kCtrLong];
-    const int inner = C - 6 * a.superstep;
+    const int inner = C - 2 * a.hw * a.superstep;
     __shared__ int s_kind, s_x, s_y, s_last, s_pos;
     bool p2_open = true;  // thread 0's view of the on-chip queue
     while (nlong > 0) {
@@ -641,7 +729,7 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
         __syncthreads();
         if (kind == 0) break;  // uniform
         if (kind == 2) {
-            whole_tube<P, B>(a, jl, F, G, C, s_bad);
+            whole_tube<P, B, SUB>(a, jl, F, G, C, s_bad);
             continue;
         }
         // chunk k of the queued pass of long tube jl
@@ -663,11 +751,11 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
             const int L = (int)(a.offsets[t + 1] - a.offsets[t]);
             const int c1 = c0 + inner < L ? c0 + inner : L;
             const double omega = 1.0 / a.tau[t], n_rot = a.n_rot[t];
-            const int ran = run_chunk<P, B>(F, G, C, reinterpret_cast<const P *>(a.f[p & 1]),
+            const int ran = run_chunk<P, B, SUB>(F, G, C, reinterpret_cast<const P *>(a.f[p & 1]),
                                             reinterpret_cast<const P *>(a.g[p & 1]),
                                             reinterpret_cast<P *>(a.f[(p + 1) & 1]),
                                             reinterpret_cast<P *>(a.g[(p + 1) & 1]), tot, a.offsets[t], L, c0,
-                                            c1, sp, (P)omega, omega, n_rot, s_bad);
+                                            c1, sp, (P)omega, omega, n_rot, a.m, a.hw, s_bad);
             const int fail = s_bad[0] > s_bad[1] ? s_bad[0] : s_bad[1];
             if (threadIdx.x == 0 && fail)
                 __hip_atomic_fetch_min(&a.fail_at[t], fail_key(done + ran, fail), __ATOMIC_RELAXED,
@@ -718,7 +806,7 @@ __global__ void __launch_bounds__(B) k_batch(BatchArgs a) {
         const int item = s_item;
         __syncthreads();
         if (item >= nwhole) break;  // uniform: every workgroup reaches this exit
-        whole_tube<P, B>(a, item, F, G, C, s_bad);
+        whole_tube<P, B, SUB>(a, item, F, G, C, s_bad);
     }
 }
 
@@ -749,11 +837,12 @@ lbm_status bvalidate(const lbm_batch_desc *d) {
     if (d->block != 0 && d->block != 256 && d->block != 512 && d->block != 1024)
         return bfail(LBM_EINVAL, "block must be 0, 256, 512 or 1024");
     if (d->superstep < 0 || d->superstep > 128) return bfail(LBM_EINVAL, "superstep must be in [0, 128]");
+    if (d->g_substeps < 0 || d->g_substeps > 64) return bfail(LBM_EINVAL, "g_substeps must be in [0, 64]");
     return LBM_OK;
 }
 
 struct Launch {
-    int block, chunk, superstep;
+    int block, chunk, superstep, m, hw;
     size_t lds;
 };
 
@@ -775,20 +864,27 @@ lbm_status plan(const lbm_batch_desc *d, Launch *L) {
         if (d->chunk < 64) return bfail(LBM_EINVAL, "chunk must be >= 64");
         if (d->chunk / 64 * 64 < C) C = d->chunk / 64 * 64;
     }
-    const int S = d->superstep ? d->superstep : 24;
-    if (C - 6 * S < 64) return bfail(LBM_EINVAL, "superstep too large for the chunk");
+    // A step reaches 3 nodes (streaming) and 2 m nodes (m rotational
+    // advection sub-steps): chunk halos of hw nodes per step of a pass.
+    const int m = d->g_substeps > 1 ? d->g_substeps : 1;
+    const int hw = 2 * m > 3 ? 2 * m : 3;
+    int S = d->superstep ? d->superstep : 24;
+    if (!d->superstep && C - 2 * hw * S < 64) S = (C - 64) / (2 * hw);
+    if (S < 1 || C - 2 * hw * S < 64) return bfail(LBM_EINVAL, "superstep too large for the chunk");
     L->block = B;
     L->chunk = C;
     L->superstep = S;
+    L->m = m;
+    L->hw = hw;
     L->lds = 28 * sz * (size_t)C;
     return LBM_OK;
 }
 
 // prepare = true: raise the kernel's dynamic-LDS limit (outside capture);
 // prepare = false: launch.
-template <typename P, int B> hipError_t launch_batch_t(const lbmx::BatchArgs &a, size_t lds, int grid,
-                                                       hipStream_t s, bool prepare) {
-    auto kern = lbmx::k_batch<P, B>;
+template <typename P, int B, bool SUB> hipError_t launch_batch_t(const lbmx::BatchArgs &a, size_t lds, int grid,
+                                                                 hipStream_t s, bool prepare) {
+    auto kern = lbmx::k_batch<P, B, SUB>;
     if (prepare)
         return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds);
@@ -796,12 +892,16 @@ template <typename P, int B> hipError_t launch_batch_t(const lbmx::BatchArgs &a,
     return hipGetLastError();
 }
 
+template <typename P, bool SUB> hipError_t launch_batch_ps(const Launch &L, const lbmx::BatchArgs &a, int grid,
+                                                          hipStream_t s, bool prepare) {
+    if (L.block == 256) return launch_batch_t<P, 256, SUB>(a, L.lds, grid, s, prepare);
+    if (L.block == 512) return launch_batch_t<P, 512, SUB>(a, L.lds, grid, s, prepare);
+    if (L.block == 1024) return launch_batch_t<P, 1024, SUB>(a, L.lds, grid, s, prepare);
+    return hipErrorInvalidValue;
+}
 template <typename P> hipError_t launch_batch_p(const Launch &L, const lbmx::BatchArgs &a, int grid,
                                                 hipStream_t s, bool prepare) {
-    if (L.block == 256) return launch_batch_t<P, 256>(a, L.lds, grid, s, prepare);
-    if (L.block == 512) return launch_batch_t<P, 512>(a, L.lds, grid, s, prepare);
-    if (L.block == 1024) return launch_batch_t<P, 1024>(a, L.lds, grid, s, prepare);
-    return hipErrorInvalidValue;
+    return L.m > 1 ? launch_batch_ps<P, true>(L, a, grid, s, prepare) : launch_batch_ps<P, false>(L, a, grid, s, prepare);
 }
 
 // Instantiated graphs of lbm_batch_step, keyed by the device and every
@@ -822,7 +922,7 @@ bool same_desc(const lbm_batch_desc &x, const lbm_batch_desc &y) {
            x.tau == y.tau && x.nsteps == y.nsteps && x.f[0] == y.f[0] && x.f[1] == y.f[1] &&
            x.g[0] == y.g[0] && x.g[1] == y.g[1] && x.status == y.status &&
            x.workspace == y.workspace && x.steps_done == y.steps_done && x.block == y.block && x.chunk == y.chunk &&
-           x.superstep == y.superstep;
+           x.superstep == y.superstep && x.g_substeps == y.g_substeps;
 }
 
 // Scratch of lbm_batch_step_noalloc: the workspace of the batched launch
@@ -881,6 +981,8 @@ hipError_t enqueue_batch(const lbm_batch_desc *d, const Launch &L, hipStream_t s
     a.total = (uint32_t)d->total_nodes;
     a.chunk = L.chunk;
     a.superstep = L.superstep;
+    a.m = L.m;
+    a.hw = L.hw;
     int dev = 0, cus = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

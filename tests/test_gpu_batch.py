@@ -39,31 +39,35 @@ def _mild_batch(seed, lengths=LENGTHS):
     return n_rot, tau, steps, rho, u, T, fields
 
 
-def _oracle_tube(fields, n_rot, tau, steps):
+def _oracle_tube(fields, n_rot, tau, steps, g_substeps=1):
     rho, u, T = fields
-    G = oracle.Grid(oracle.D1Q7, (len(rho),), bc=(oracle.OPEN,), n_rot=n_rot, tau=tau)
+    G = oracle.Grid(oracle.D1Q7, (len(rho),), bc=(oracle.OPEN,), n_rot=n_rot, tau=tau, g_substeps=g_substeps)
     f, g = G.init_eq(rho, u, T)
     G.step(f, g, steps)
     return G.moments(f, g)[:3]
 
 
-@pytest.mark.parametrize("dtype,chunk,superstep", [("float64", 0, 0), ("float64", 256, 8),
-                                                   ("float32", 0, 0), ("float32", 448, 16)])
-def test_batch_matches_oracle_per_tube(torch_cuda, dtype, chunk, superstep):
+@pytest.mark.parametrize("dtype,chunk,superstep,m", [("float64", 0, 0, 1), ("float64", 256, 8, 1),
+                                                     ("float32", 0, 0, 1), ("float32", 448, 16, 1),
+                                                     ("float64", 0, 0, 4), ("float64", 512, 6, 3),
+                                                     ("float32", 0, 0, 4), ("float32", 640, 8, 5)])
+def test_batch_matches_oracle_per_tube(torch_cuda, dtype, chunk, superstep, m):
     """chunk=0: the library's capacity (most tubes on chip in one piece);
-    small chunks force the halo'd multi-pass path for the long tubes."""
+    small chunks force the halo'd multi-pass path for the long tubes.  m > 1:
+    the rotational advection in m sub-steps (halos of max(3, 2m) nodes per
+    step), against the oracle's sub-stepped update."""
     from paper_1606_06107_amd import Batch
-    announce(f"batch {dtype} chunk={chunk} superstep={superstep}")
+    announce(f"batch {dtype} chunk={chunk} superstep={superstep} g_substeps={m}")
     n_rot, tau, steps, rho, u, T, fields = _mild_batch(1)
     b = Batch(LENGTHS, n_rot, tau, steps, dtype=getattr(torch_cuda, dtype), chunk=chunk,
-              superstep=superstep).init(rho, u, T)
+              superstep=superstep, g_substeps=m).init(rho, u, T)
     b.step()
     r, uu, TT = b.moments()
     torch_cuda.cuda.synchronize()
     assert (b.status.cpu().numpy() == 0).all()
     R, U, Tt = b.split(r), b.split(uu), b.split(TT)
     for i, L in enumerate(LENGTHS):
-        ro, uo, To = _oracle_tube(fields[i], n_rot[i], tau[i], int(steps[i]))
+        ro, uo, To = _oracle_tube(fields[i], n_rot[i], tau[i], int(steps[i]), m)
         if dtype == "float64":
             assert np.abs(R[i] - ro).max() <= 1e-12 * np.abs(ro).max(), i
             assert np.abs(U[i] - uo[0]).max() <= 1e-12 * max(np.abs(uo).max(), 1.0), i
@@ -189,3 +193,29 @@ def test_index_order_mode_beyond_sort_capacity(torch_cuda):
     for a_, b_ in ((R[0], ro), (U[0], uo[0]), (TT[0], To)):
         assert np.abs(a_ - b_).max() <= 1e-5
     assert max(np.abs(R[i] - 1.0).max() for i in range(1, I, 997)) < 1e-6
+
+
+def test_batch_substeps_equal_per_step_path_and_noalloc(torch_cuda):
+    """The batch kernel's sub-stepped rotational advection equals the
+    per-step path's (lbm_step with g_substeps) on a tube, and the
+    no-allocation launch gives the same bits as the graph launch."""
+    import torch
+    from paper_1606_06107_amd import Batch, Sim
+    announce("batch substeps == per-step substeps")
+    L, steps, m = 700, 60, 4
+    rho, u, T = workloads.sod_tube(L, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    sim = Sim((L,), bc=["open"], n_rot=4.0, tau=1.0, dtype=torch.float64, g_substeps=m).init(rho, u, T)
+    sim.step(steps)
+    r1, u1, T1, _ = sim.moments()
+    outs = []
+    for noalloc in (False, True):
+        b = Batch([L], [4.0], [1.0], [steps], dtype=torch.float64, g_substeps=m).init(rho, u[0], T)
+        (b.step_noalloc if noalloc else b.step)()
+        r2, u2, T2 = b.moments()
+        torch.cuda.synchronize()
+        assert int(b.status.cpu()[0]) == 0
+        outs.append(torch.stack([r2, u2, T2]).cpu().numpy())
+        b.release()
+    ref = np.stack([r1.cpu().numpy(), u1[0].cpu().numpy(), T1.cpu().numpy()])
+    assert np.abs(outs[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.array_equal(outs[0], outs[1])
