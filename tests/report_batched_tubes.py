@@ -11,7 +11,8 @@ Courant number |u*| / r of the star state against the linear stability
 limit of the forward-Euler upwind update at the tube's omega = 1/tau, and
 the sign of the fourth-order translational equilibrium at the two star
 states of the exact solution.  Plus the batch kernel's throughput over the stable tubes
-alone.
+alone, and the same tubes with the rotational advection in 2, 4 and 8
+sub-steps.
 
 Not collected by pytest (a GPU report, not a test).  Usage, from the
 repository root on a GPU machine:
@@ -146,6 +147,52 @@ def main(out_md):
     work = float((sub.lengths * sub.steps).sum())
     assert (b.status.cpu().numpy() == 0).all()
 
+    # the same tubes with the rotational advection in m sub-steps (g_substeps):
+    # FP64 status and accuracy against the exact solution, FP32 time over the
+    # tubes that complete
+    subrows = []
+    for m in (2, 4, 8):
+        b = Batch(bt.lengths, bt.n_rot, bt.tau, bt.steps, dtype=torch.float64, block=512, g_substeps=m)
+        b.init(bt.rho, bt.u[0], bt.T).step()
+        torch.cuda.synchronize()
+        stm = b.status.cpu().numpy()
+        r, u, T = b.moments()
+        fm = [b.split(x) for x in (r, u, T)]
+        b.release()
+        del b
+        ok = np.nonzero(stm == 0)[0]
+        ex_m = []
+        for i in ok:
+            L = int(bt.lengths[i])
+            t = float(bt.steps[i]) / (L * r_lat)
+            x = (np.arange(L) + 0.5) / L
+            ra, ua, pa = riemann.sample(tuple(bt.left[i]), tuple(bt.right[i]), float(bt.gamma[i]), (x - 0.5) / t)
+            ex_m.append([l1_rel_error(fm[0][i], ra), l1_rel_error(fm[1][i], ua),
+                         l1_rel_error(fm[0][i] * fm[2][i], pa)])
+        ex_m = np.array(ex_m)
+        rescued = int(((stm == 0) & (st64 != 0)).sum())
+        lost = int(((stm != 0) & (st64 == 0)).sum())
+        sm = bt.subset(ok)
+        b = Batch(sm.lengths, sm.n_rot, sm.tau, sm.steps, dtype=torch.float32, block=1024, g_substeps=m)
+        b.init(sm.rho, sm.u[0], sm.T).step()
+        b.init(sm.rho, sm.u[0], sm.T)
+        a_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a_.record(b.stream)
+        b.step()
+        e_.record(b.stream)
+        torch.cuda.synchronize()
+        ms_m = a_.elapsed_time(e_)
+        n32 = int((b.status.cpu().numpy() == 0).sum())
+        work_m = float((sm.lengths * b.steps_done.cpu().numpy()).sum())  # steps actually executed
+        b.release()
+        del b
+        torch.cuda.empty_cache()
+        subrows.append((m, len(ok), rescued, lost, np.median(ex_m, 0), np.percentile(ex_m, 90, 0), n32, ms_m,
+                        work_m))
+        print(f"g_substeps {m}: {len(ok)} FP64-stable ({rescued} rescued, {lost} lost), FP32 {n32} of them, "
+              f"{ms_m:.2f} ms", flush=True)
+
     pct = lambda col: [float(np.percentile(rows[:, col], q)) for q in (50, 90, 99, 100)]
     lines = [
         "# Batched shock tubes (4096 tubes): per-instance errors and failure causes",
@@ -206,7 +253,22 @@ def main(out_md):
               "",
               f"The batch kernel over the {sub.num} FP32-stable tubes alone: {ms:.2f} ms for {work:.3e} node-steps "
               f"= {work / ms / 1e3:,.0f} MLUPS (the all-tube launch stops most tubes early; its MLUPS counts "
-              "the steps actually executed)."]
+              "the steps actually executed).",
+              "",
+              "## Rotational advection in m sub-steps (`g_substeps`)",
+              "",
+              "The same 4096 tubes with the rotational populations advected in m sub-steps of c/m per "
+              "time step (relaxation once per step), FP64 (block 512): tubes that complete, tubes that "
+              "complete now but not as written (rescued) and the reverse (lost), the FP64-vs-exact "
+              "relative L1 of rho / u / p over the completed tubes, and the FP32 kernel over those tubes "
+              "(block 1024; how many complete in FP32, its time and rate).",
+              "",
+              "| m | FP64 completed | rescued | lost | exact L1 p50 rho / u / p | exact L1 p90 rho / u / p "
+              "| FP32 completed | FP32 ms | MLUPS |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    for m, n_ok, resc, lost, p50, p90, n32, ms_m, work_m in subrows:
+        lines.append(f"| {m} | {n_ok} | {resc} | {lost} | " + " / ".join(f"{v:.2e}" for v in p50) + " | "
+                     + " / ".join(f"{v:.2e}" for v in p90) + f" | {n32} | {ms_m:.2f} | {work_m / ms_m / 1e3:,.0f} |")
     with open(os.path.join(ROOT, out_md), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
