@@ -463,8 +463,8 @@ def extra_batch(seed=0):
     return out
 
 
-def extra_surrogate(train_candidates=8192, test_candidates=4096, test_tubes=256, train_steps=30000, calls=16,
-                    pairs_per_tube=16, train_batch=32, lr=3e-3, plain_calls=1):
+def extra_surrogate(train_candidates=20480, test_candidates=4096, test_tubes=256, train_steps=90000, calls=16,
+                    pairs_per_tube=16, train_batch=32, lr=2e-3, plain_calls=1, val_tubes=64, val_every=7500):
     """Learned surrogate vs plain LBM on held-out 4096-node tubes: 16 calls
     of k = 16 steps (256 steps) from the initial state; the first
     `plain_calls` calls run the plain scheme (the initial diaphragm is a
@@ -472,28 +472,54 @@ def extra_surrogate(train_candidates=8192, test_candidates=4096, test_tubes=256,
     and plain-LBM fallback; errors judged against the plain LBM run (Sec. VI
     relative L1 per tube, averaged over the tubes).  Trained on the times
     such a rollout visits: 16 pairs per training tube from its initial
-    state."""
+    state; the checkpoint kept is the one with the lowest velocity error of
+    the same rollout (no fallback) on `val_tubes` validation tubes drawn
+    from a third seed; the admission check's Mach bound is the largest
+    |u|/sqrt(T) of the training pairs (predictions outside the trained
+    states go to the plain scheme)."""
     import numpy as np
     import torch
 
     from paper_1606_06107_amd import Batch, Surrogate
     from paper_1606_06107_amd import surrogate as SG
+
+    def l1(p, q):
+        return (torch.abs(p - q).sum(-1) / torch.abs(q).sum(-1).clamp_min(1e-300)).mean(1).cpu().numpy()
+
+    def held_out(seed, n):
+        te = SG.stable_tubes(test_candidates, seed=seed)
+        te = te.subset(np.arange(min(n, te.num)))
+        x0 = torch.as_tensor(np.stack([te.rho, te.u[0], te.T]).reshape(3, te.num, 4096), device="cuda")
+        gamma = torch.as_tensor(te.gamma, device="cuda")
+        plain = Batch(te.lengths, te.n_rot, te.tau, np.full(te.num, 16 * calls), dtype=torch.float32)
+        plain.init(te.rho, te.u[0], te.T)
+        # the fallback runs the few rejected tubes' remaining steps: latency-bound,
+        # so one node per thread in 1024-node chunks
+        fb = Batch(te.lengths, te.n_rot, te.tau, np.zeros(te.num, dtype=np.int64), dtype=torch.float32,
+                   chunk=1024)
+        return te, x0, gamma, plain, fb
+
     t0 = time.perf_counter()
     bt = SG.stable_tubes(train_candidates, seed=0)
     x, tg, gm = SG.make_pairs(bt, pairs_per_tube=pairs_per_tube, seed=1, start="zero")
+    envelope = SG.mach_envelope(x, tg)
+    tv, x0v, gv, plain_v, fbv = held_out(2 * 10 ** 6, val_tubes)
+    ref_v = SG.fields_of(plain_v.step()).clone()
+    del plain_v
     sur = Surrogate(train_batch, 4096)
     sur.set_params(SG.init_params(0))
-    hist = SG.train(sur, x, tg, gm, steps=train_steps, lr=lr, log_every=train_steps // 4)
+    sur_v = sur.shape_like(tv.num)
+
+    def validate():
+        xr, _ = SG.rollout(sur_v, x0v, gv, fbv, calls, fallback=False, plain_calls=plain_calls)
+        return float(l1(xr, ref_v)[1])
+    hist = SG.train(sur, x, tg, gm, steps=train_steps, lr=lr, validate=validate, validate_every=val_every)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del x, tg
-    te = SG.stable_tubes(test_candidates, seed=10 ** 6)
-    te = te.subset(np.arange(min(test_tubes, te.num)))
+    del x, tg, sur_v, fbv
+    te, x0, gamma, plain, fb = held_out(10 ** 6, test_tubes)
     B = te.num
-    x0 = torch.as_tensor(np.stack([te.rho, te.u[0], te.T]).reshape(3, B, 4096), device="cuda")
-    gamma = torch.as_tensor(te.gamma, device="cuda")
-    plain = Batch(te.lengths, te.n_rot, te.tau, np.full(B, 16 * calls), dtype=torch.float32)
-    plain.init(te.rho, te.u[0], te.T).step()  # warm (graph capture)
+    plain.step()  # warm (graph capture)
     plain.init(te.rho, te.u[0], te.T)
     a, e = _events(plain.stream)
     torch.cuda.synchronize()
@@ -504,25 +530,20 @@ def extra_surrogate(train_candidates=8192, test_candidates=4096, test_tubes=256,
     t_lbm = a.elapsed_time(e)
     ref = SG.fields_of(plain)
     surB = sur.shape_like(B)
-    # the fallback runs the few rejected tubes' remaining steps: latency-bound,
-    # so one node per thread in 1024-node chunks (measured 1.1 ms against 1.4 ms
-    # for the throughput shape's 1344-node chunks)
-    fb = Batch(te.lengths, te.n_rot, te.tau, np.zeros(B, dtype=np.int64), dtype=torch.float32, chunk=1024)
-    SG.rollout(surB, x0, gamma, fb, calls, plain_calls=plain_calls)  # warm
+    SG.rollout(surB, x0, gamma, fb, calls, plain_calls=plain_calls, max_mach=envelope)  # warm
     a, e = _events(plain.stream)
     torch.cuda.synchronize()
     a.record(plain.stream)
-    xr, acc = SG.rollout(surB, x0, gamma, fb, calls, plain_calls=plain_calls)
+    xr, acc = SG.rollout(surB, x0, gamma, fb, calls, plain_calls=plain_calls, max_mach=envelope)
     e.record(plain.stream)
     torch.cuda.synchronize()
     t_sur = a.elapsed_time(e)
-
-    def l1(p, q):
-        return (torch.abs(p - q).sum(-1) / torch.abs(q).sum(-1).clamp_min(1e-300)).mean(1).cpu().numpy()
     err, err_id = l1(xr, ref), l1(x0, ref)
     per_tube_u = (torch.abs(xr[1] - ref[1]).sum(-1) / torch.abs(ref[1]).sum(-1)).cpu().numpy()
     xn, _ = SG.rollout(surB, x0, gamma, fb, calls, fallback=False, plain_calls=plain_calls)
     err_nf = l1(xn, ref)
+    xm, accm = SG.rollout(surB, x0, gamma, fb, calls, plain_calls=plain_calls)  # the default 0.9 bound
+    err_m09 = l1(xm, ref)
     xs, _ = SG.rollout(surB, x0, gamma, fb, calls, fallback=False)
     err_all = l1(xs, ref)
     # one call (16 steps) from the initial fields against 16 plain steps
@@ -548,7 +569,10 @@ def extra_surrogate(train_candidates=8192, test_candidates=4096, test_tubes=256,
                         f"{plain_calls} by the plain scheme",
             "train": {"candidate_tubes": train_candidates, "stable_tubes": int(bt.num),
                       "pairs": int(bt.num * pairs_per_tube), "batch": train_batch, "adam_steps": train_steps,
-                      "seconds": round(t_train, 2), "loss": hist},
+                      "lr": lr, "seconds": round(t_train, 2),
+                      "step_loss_validation_u_l1": [[h[0], float(f"{h[1]:.3g}"), round(h[2], 5)] for h in hist],
+                      "validation_tubes": int(tv.num)},
+            "max_mach_envelope": round(envelope, 4),
             "t_lbm_ms": round(t_lbm, 3), "t_surrogate_with_fallback_ms": round(t_sur, 3),
             "speedup": round(t_lbm / t_sur, 3), "plain_calls": plain_calls,
             "surrogate_tube_calls_fraction": round(sum(acc_l) / max(B * sur_calls, 1), 4),
@@ -562,6 +586,8 @@ def extra_surrogate(train_candidates=8192, test_candidates=4096, test_tubes=256,
                                   "p90": round(float(np.percentile(per_tube_u, 90)), 5),
                                   "max": round(float(per_tube_u.max()), 5)},
             "rel_l1_no_fallback": [round(float(v), 5) for v in err_nf],
+            "with_max_mach_0.9": {"rel_l1_rho_u_T": [round(float(v), 5) for v in err_m09],
+                                  "tubes_handed_to_plain_scheme": int(B - int(accm[-1].item()))},
             "rel_l1_surrogate_every_call": [round(float(v), 5) for v in err_all],
             "rel_l1_identity": [round(float(v), 5) for v in err_id],
             "one_call_rel_l1": [round(float(v), 5) for v in err_one],
@@ -600,14 +626,100 @@ def extra_hbm(steps=40, warmup=10, sizes=((1024, 1024), (4096, 2048))):
             gbs = N * 448 / (ms * 1e-3) / 1e9
             ok = bool(torch.isfinite(sim.moments(totals=False)[2]).all().item())
             ws = N * (49 * (1 if inplace else 2) + 14) * 4
+            del sim
+            torch.cuda.empty_cache()
+            probe = pattern_probe(nx, ny, inplace, steps)
+            best = max(probe.values())
             rows.append({"nodes": f"{nx}x{ny}", "streaming": "in-place" if inplace else "ping-pong",
                          "working_set_MB": round(ws / 1e6, 1), "tile": list(tile[:2]),
                          "ms_per_step": round(ms, 4), "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1),
-                         "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok})
-            del sim
-            torch.cuda.empty_cache()
+                         "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok,
+                         "pattern_probe_GBps_by_policy": probe, "frac_of_pattern_probe": round(gbs / best, 4)})
     return {"workload": "headline 2-D step (D2Q49+D1Q7 FP32, 448 B per node-step) at a cache-sized and "
-                        "an HBM-sized grid", "rows": rows}
+                        "an HBM-sized grid; each beside the memory-only probe of its access pattern "
+                        "(lbm_pattern_probe, best of its cache policies)", "rows": rows}
+
+
+def extra_placement(holds=8, hold_mb=192, steps=40):
+    """The in-place 1024^2 step and its memory-only probe, re-allocated after
+    each of `holds` further allocations of `hold_mb` MB (kept alive), so that
+    each run lands on other physical pages.  Its 264 MB working set is about
+    the size of the 256 MB memory-side cache; whether it stays resident
+    depends on where the pages land."""
+    import torch
+
+    import workloads
+    from paper_1606_06107_amd import Sim
+    w = workloads.Periodic2D()
+    fields = w.fields()
+    N = w.nx * w.ny
+    hold, rows = [], []
+    for k in range(holds):
+        sim = Sim((w.nx, w.ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*fields)
+        sim.set_tile(128, 2)
+        sim.step(10)
+        sim.prepare(steps)
+        a, b = _events(sim.stream)
+        torch.cuda.synchronize()
+        a.record(sim.stream)
+        sim.step(steps)
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) / steps * 1e3
+        del sim
+        torch.cuda.empty_cache()
+        probe = pattern_probe(w.nx, w.ny, True, steps)
+        rows.append({"held_MB": k * hold_mb, "step_us": round(us, 1), "step_GBps": round(N * 448 / us / 1e3, 1),
+                     "probe_GBps_by_policy": probe})
+        hold.append(torch.empty(hold_mb * 2 ** 20, dtype=torch.uint8, device="cuda"))
+    del hold
+    torch.cuda.empty_cache()
+    return {"workload": "1024^2 in place (D2Q49+D1Q7 FP32, tile 128x2) re-allocated after growing allocations",
+            "rows": rows}
+
+
+def pattern_probe(nx, ny, inplace, launches=40):
+    """The step's memory pattern with no arithmetic (lbm_pattern_probe) on an
+    nx x ny grid: ping-pong (alternating buffers) or in place (even and odd
+    launches alternating); GB/s at 448 B per node and launch, for each cache
+    policy (default, non-temporal loads of f, non-temporal loads and stores
+    of f, non-temporal loads and stores of g only)."""
+    import ctypes
+
+    import torch
+
+    from paper_1606_06107_amd import _lib
+    lib = _lib.load()
+    N = nx * ny
+    f = [torch.zeros(49 * N, device="cuda") for _ in range(1 if inplace else 2)]
+    g = [torch.zeros(7 * N, device="cuda") for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def launch(k, pol):
+        if inplace:
+            mode, fd, fs = 1 + (k & 1), f[0], f[0]
+        else:
+            mode, fd, fs = 0, f[(k + 1) & 1], f[k & 1]
+        _lib.check(lib.lbm_pattern_probe(mode, pol, ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(fs.data_ptr()),
+                                         ctypes.c_void_p(g[(k + 1) & 1].data_ptr()),
+                                         ctypes.c_void_p(g[k & 1].data_ptr()), nx, ny,
+                                         ctypes.c_void_p(stream.cuda_stream)))
+    for pol, name in ((0, "default"), (1, "nt_loads"), (2, "nt_loads_stores"), (3, "nt_rotational")):
+        for k in range(4):
+            launch(k, pol)
+        a, b = _events(stream)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for k in range(launches):
+            launch(k, pol)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / launches
+        out[name] = round(N * 448 / (ms * 1e-3) / 1e9, 1)
+    del f, g
+    torch.cuda.empty_cache()
+    return out
 
 
 def tile_sweep(nx, ny, steps, inplace):
@@ -652,9 +764,9 @@ def main():
                     default="hbm,tube_1d,turbulence_3d,d2q37,fd,transport,batched_tubes,surrogate",
                     help="comma-separated subset of the extra workloads to run")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--sur-train-steps", type=int, default=30000,
+    ap.add_argument("--sur-train-steps", type=int, default=90000,
                     help="Adam steps of the surrogate extra's training")
-    ap.add_argument("--sur-train-candidates", type=int, default=8192,
+    ap.add_argument("--sur-train-candidates", type=int, default=20480,
                     help="seeded tubes generated for the surrogate's training (the stable ones are used)")
     ap.add_argument("--ping-pong", action="store_true",
                     help="two translational buffers instead of in-place streaming")
@@ -772,7 +884,7 @@ def main():
         extra = {}
         wanted = set(args.extras.split(","))
         for name, fn in (("hbm", extra_hbm), ("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d),
-                         ("turbulence_3d_full", extra_3d_full),
+                         ("turbulence_3d_full", extra_3d_full), ("placement", extra_placement),
                          ("d2q37", extra_d2q37), ("fd", extra_fd),
                          ("transport", extra_transport), ("batched_tubes", extra_batch),
                          ("surrogate", lambda: extra_surrogate(train_steps=args.sur_train_steps,

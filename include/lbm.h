@@ -240,6 +240,22 @@ const char *lbm_last_error(void);
  * LBM_ELAUNCH. */
 lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* Memory pattern of the 2-D D2Q49 + D1Q7 FP32 step with no arithmetic, on an
+ * nx x ny periodic grid (4 <= nx, 4 <= ny <= 65535): 49 translational rows
+ * f[49][nx*ny] and 7 rotational rows g[7][nx*ny] (x fastest), device
+ * buffers.  Slot i has velocity (i % 7 - 3, i / 7 - 3), slot 48 - i the
+ * opposite.  mode 0 (ping-pong, f_dst != f_src): f_dst[i](x) =
+ * f_src[i](x - c_i); mode 1 (in place, even step, f_dst == f_src):
+ * f[48 - i](x) = f[i](x); mode 2 (in place, odd step, f_dst == f_src):
+ * f[i](x + c_i) = f[48 - i](x - c_i).  Every mode copies g_src to g_dst
+ * (distinct).  policy 0: default cache policy; 1: non-temporal loads of f;
+ * 2: non-temporal loads and stores of f; 3: default policy for f,
+ * non-temporal loads and stores of g.  448 B of memory traffic per node,
+ * as the step.  Not part of the scheme: the pattern's bandwidth ceiling that
+ * the step kernels are set against.  Errors: LBM_EINVAL, LBM_ELAUNCH. */
+lbm_status lbm_pattern_probe(int32_t mode, int32_t policy, float *f_dst, const float *f_src, float *g_dst,
+                             const float *g_src, int32_t nx, int32_t ny, void *hip_stream);
+
 /* Lattice constants the library computes with: Q, r, and (if not NULL) the
  * weights w[Q] and velocities c[Q][3] (integers) of the population slots in
  * storage order (populations[Q][N] of lbm_populations / lbm_init_populations;

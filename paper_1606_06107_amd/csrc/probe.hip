@@ -1,8 +1,12 @@
-// Plain device copy (lbm_stream_copy in include/lbm.h): the memory-bandwidth
-// reference the step kernels are compared with.  One 16-byte load and store
-// per thread in a single pass over the buffer -- on MI355X the fastest of
-// the simple copy shapes (grid-stride loops, several vectors per thread and
-// non-temporal hints measured 4.5-5.8 TB/s for 2 GiB, this shape 6.2 TB/s).
+// Memory-bandwidth references the step kernels are compared with (not part
+// of the scheme):
+//  - lbm_stream_copy: plain device copy.  One 16-byte load and store per
+//    thread in a single pass over the buffer -- on MI355X the fastest of the
+//    simple copy shapes (grid-stride loops, several vectors per thread and
+//    non-temporal hints measured 4.5-5.8 TB/s for 2 GiB, this shape 6.2 TB/s).
+//  - lbm_pattern_probe: the 2-D D2Q49 + D1Q7 step's memory pattern with no
+//    arithmetic (49 translational rows gathered from the 7 x 7 neighbourhood
+//    and stored, 7 rotational rows copied), in the three storage schemes.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -22,7 +26,100 @@ __global__ void __launch_bounds__(256) k_stream_copy(const f32x4 *__restrict__ s
     if (i < n) dst[i] = src[i];
 }
 
+// One node per thread, 256 nodes of one grid row per workgroup.  Slot i has
+// velocity (i % 7 - 3, i / 7 - 3); slot 48 - i has the opposite one.
+//   MODE 0 ping-pong: fd[i](x) = fs[i](x - c_i), periodic wrap.
+//   MODE 1 in place, even step: f[48 - i](x) = f[i](x).
+//   MODE 2 in place, odd step: f[i](x + c_i) = f[48 - i](x - c_i)
+//     (thread x reads and writes the same 49 locations, so no two threads
+//     touch one location).
+// POL 0: default cache policy; 1: non-temporal loads of f; 2: non-temporal
+// loads and stores of f; 3: default for f, non-temporal loads and stores of
+// g.  Otherwise g rows are copied with the default policy.
+template <int MODE, int POL>
+__global__ void __launch_bounds__(256) k_pattern_2d(const float *fs, float *fd, const float *__restrict__ gs,
+                                                   float *__restrict__ gd, int nx, int ny) {
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= nx) return;
+    const size_t N = (size_t)nx * ny;
+    auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+    auto at = [&](int i, int xx, int yy) { return (size_t)i * N + (size_t)wrap(yy, ny) * nx + wrap(xx, nx); };
+    float v[49];
+#pragma unroll
+    for (int i = 0; i < 49; ++i) {
+        const int cx = i % 7 - 3, cy = i / 7 - 3;
+        const size_t src = MODE == 0 ? at(i, x - cx, y - cy) : MODE == 1 ? at(i, x, y) : at(48 - i, x - cx, y - cy);
+        v[i] = POL == 1 || POL == 2 ? __builtin_nontemporal_load(fs + src) : fs[src];
+    }
+#pragma unroll
+    for (int i = 0; i < 49; ++i) {
+        const int cx = i % 7 - 3, cy = i / 7 - 3;
+        const size_t dst = MODE == 0 ? at(i, x, y) : MODE == 1 ? at(48 - i, x, y) : at(i, x + cx, y + cy);
+        if (POL == 2)
+            __builtin_nontemporal_store(v[i], fd + dst);
+        else
+            fd[dst] = v[i];
+    }
+    const size_t o = (size_t)y * nx + x;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        if (POL == 3)
+            __builtin_nontemporal_store(__builtin_nontemporal_load(gs + (size_t)j * N + o), gd + (size_t)j * N + o);
+        else
+            gd[(size_t)j * N + o] = gs[(size_t)j * N + o];
+    }
+}
+
+template <int MODE>
+static void launch_pattern(int pol, dim3 grid, hipStream_t s, const float *fs, float *fd, const float *gs, float *gd,
+                           int nx, int ny) {
+    if (pol == 0)
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 0>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+    else if (pol == 1)
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 1>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+    else if (pol == 2)
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 2>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+    else
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 3>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+}
+
 }  // namespace lbmx
+
+extern "C" lbm_status lbm_pattern_probe(int32_t mode, int32_t policy, float *f_dst, const float *f_src,
+                                        float *g_dst, const float *g_src, int32_t nx, int32_t ny,
+                                        void *hip_stream) {
+    if (!f_dst || !f_src || !g_dst || !g_src) {
+        lbmx::set_error("lbm_pattern_probe: NULL buffer");
+        return LBM_EINVAL;
+    }
+    if (mode < 0 || mode > 2 || policy < 0 || policy > 3) {
+        lbmx::set_error("lbm_pattern_probe: mode must be 0, 1 or 2 and policy 0 to 3");
+        return LBM_EINVAL;
+    }
+    if ((mode == 0) == (f_dst == f_src) || g_dst == g_src) {
+        lbmx::set_error("lbm_pattern_probe: mode 0 needs distinct f buffers, modes 1 and 2 one buffer; "
+                        "g buffers must be distinct");
+        return LBM_EINVAL;
+    }
+    if (nx < 4 || ny < 4 || ny > 65535 || (int64_t)nx * ny * 49 >= (int64_t)1 << 40) {
+        lbmx::set_error("lbm_pattern_probe: need 4 <= nx, 4 <= ny <= 65535");
+        return LBM_EINVAL;
+    }
+    const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)ny);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if (mode == 0)
+        lbmx::launch_pattern<0>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+    else if (mode == 1)
+        lbmx::launch_pattern<1>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+    else
+        lbmx::launch_pattern<2>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        lbmx::set_error((std::string("lbm_pattern_probe: ") + hipGetErrorString(e)).c_str());
+        return LBM_ELAUNCH;
+    }
+    return LBM_OK;
+}
 
 extern "C" lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream) {
     if (!dst || !src) {

@@ -234,3 +234,16 @@ def test_stream_copy_rejects_unaligned(lib):
     assert L.lbm_stream_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 32, None) == lib.LBM_EINVAL
     assert L.lbm_stream_copy(None, ctypes.c_void_p(0x2000), 32, None) == lib.LBM_EINVAL
     assert L.lbm_stream_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 0, None) == lib.LBM_OK
+
+
+def test_pattern_probe_rejects_bad_arguments(lib):
+    L = lib.load()
+    a, b, c, d = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x4000))
+    assert L.lbm_pattern_probe(0, 0, a, a, c, d, 64, 64, None) == lib.LBM_EINVAL   # ping-pong needs two f
+    assert L.lbm_pattern_probe(1, 0, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL   # in place needs one f
+    assert L.lbm_pattern_probe(2, 0, a, a, c, c, 64, 64, None) == lib.LBM_EINVAL   # g distinct
+    assert L.lbm_pattern_probe(3, 0, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe(0, 4, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe(0, 0, a, b, c, d, 3, 64, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe(0, 0, a, b, c, d, 64, 70000, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe(0, 0, None, b, c, d, 64, 64, None) == lib.LBM_EINVAL
