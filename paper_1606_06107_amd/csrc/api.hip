@@ -285,6 +285,10 @@ hipError_t enqueue_step(lbm_sim s, hipStream_t st) {
     a.omega = 1.0 / d.tau;
     a.n_rot = d.n_rot;
     a.ntiles = lbmx::step_ntiles(d.dim, s->tile, a.n0, a.n1, a.n2, &a.tiles0, &a.tiles1, &a.tiles2);
+    // Tile order alternates from step to step (odd in-place steps; every
+    // other ping-pong step, by buffer parity), a function of state that the
+    // graph cache keys on (layout, fcur).
+    a.reverse = s->inplace ? (a.scheme == lbmx::kSchemeInPlaceOdd ? 1 : 0) : s->fcur;
     // Monitored steps depend on t mod every only; the row they fill comes
     // from the device-side counter (set by lbm_set_monitor), so a recorded
     // graph of steps replays correctly from any start with the same phase.

@@ -46,6 +46,7 @@ struct StepArgs {
     double n_rot;       // rotational degrees of freedom
     double *partials;   // NULL, or [ntiles][2+D] FP64 per-tile totals of time t
     int tiles0, tiles1, tiles2, ntiles;
+    int reverse;        // 1: every XCD walks its band of tiles from the far end
 };
 
 // Arguments of the field/total/export kernels.

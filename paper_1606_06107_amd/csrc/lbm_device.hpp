@@ -363,11 +363,16 @@ __device__ __forceinline__ int nb_coord(int x, int d, int n, int open) {
 
 // Map a workgroup id to a tile id so that each of the 8 XCDs (which receive
 // workgroups round-robin) works on one contiguous band of tiles and shares
-// halo rows through its own L2.
-__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+// halo rows through its own L2.  reverse = 1 walks every band from its far
+// end.  Consecutive steps alternate the direction: a step then starts on
+// the nodes its predecessor touched last, which are still in the
+// memory-side cache (a working set about its size is otherwise swept in
+// the order least favourable to it).
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles, int reverse) {
     const int q = ntiles >> 3, rem = ntiles & 7;
     const int xcd = bid & 7, k = bid >> 3;
-    return xcd * q + (xcd < rem ? xcd : rem) + k;
+    const int len = q + (xcd < rem ? 1 : 0);
+    return xcd * q + (xcd < rem ? xcd : rem) + (reverse ? len - 1 - k : k);
 }
 
 // Deterministic wave64 sum (butterfly over fixed lane pairs).

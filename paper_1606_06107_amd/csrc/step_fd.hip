@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(TX *TY) k_step_fd(FdArgs a) {
     constexpr int H = Q / 2;
     constexpr uint32_t SZ = sizeof(P);
 
-    const int tile = xcd_tile(blockIdx.x, a.ntiles);
+    const int tile = xcd_tile(blockIdx.x, a.ntiles, 0);
     const int x0 = (tile % a.tiles0) * TX;
     const int y0 = D >= 2 ? (tile / a.tiles0) * TY : 0;
     const int x = x0 + (int)threadIdx.x % TX, y = y0 + (D >= 2 ? (int)threadIdx.x / TX : 0);

@@ -172,7 +172,7 @@ __attribute__((amdgpu_waves_per_eu(kWavesMin<P, D>, kWavesMax<P, D>))) k_step_12
     constexpr uint32_t SZ = sizeof(P);
     constexpr bool F32 = sizeof(P) == 4;
 
-    const int tile = xcd_tile(blockIdx.x, a.ntiles);
+    const int tile = xcd_tile(blockIdx.x, a.ntiles, a.reverse);
     const int x0 = (tile % a.tiles0) * TX;
     const int y0 = D >= 2 ? (tile / a.tiles0) * TY : 0;
     const int lx = threadIdx.x % TX, ly = D >= 2 ? threadIdx.x / TX : 0;
@@ -631,7 +631,7 @@ __global__ void __launch_bounds__(256) k_step_3(StepArgs a) {
     static_assert(TX * TY == 64, "64 nodes per workgroup");
     __shared__ double part[4][64][6];
     __shared__ double part2[4][64][8];
-    const int tile = xcd_tile(blockIdx.x, a.ntiles);
+    const int tile = xcd_tile(blockIdx.x, a.ntiles, a.reverse);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int t0 = tile % a.tiles0, rest = tile / a.tiles0;
     const int t1 = rest % a.tiles1, t2 = rest / a.tiles1;
