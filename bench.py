@@ -629,15 +629,18 @@ def extra_hbm(steps=40, warmup=10, sizes=((1024, 1024), (4096, 2048))):
             del sim
             torch.cuda.empty_cache()
             probe = pattern_probe(nx, ny, inplace, steps)
+            probe_blk = pattern_probe(nx, ny, inplace, steps, blocked=True)
             best = max(probe.values())
             rows.append({"nodes": f"{nx}x{ny}", "streaming": "in-place" if inplace else "ping-pong",
                          "working_set_MB": round(ws / 1e6, 1), "tile": list(tile[:2]),
                          "ms_per_step": round(ms, 4), "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1),
                          "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok,
-                         "pattern_probe_GBps_by_policy": probe, "frac_of_pattern_probe": round(gbs / best, 4)})
+                         "pattern_probe_GBps_by_policy": probe, "frac_of_pattern_probe": round(gbs / best, 4),
+                         "pattern_probe_64_node_blocks_GBps_by_policy": probe_blk})
     return {"workload": "headline 2-D step (D2Q49+D1Q7 FP32, 448 B per node-step) at a cache-sized and "
                         "an HBM-sized grid; each beside the memory-only probe of its access pattern "
-                        "(lbm_pattern_probe, best of its cache policies)", "rows": rows}
+                        "(lbm_pattern_probe, best of its cache policies), and the probe of the same "
+                        "pattern with f in 64-node blocks (not the kernel's layout in 2-D)", "rows": rows}
 
 
 def extra_placement(holds=8, hold_mb=192, steps=40):
@@ -678,7 +681,7 @@ def extra_placement(holds=8, hold_mb=192, steps=40):
             "rows": rows}
 
 
-def pattern_probe(nx, ny, inplace, launches=40):
+def pattern_probe(nx, ny, inplace, launches=40, blocked=False):
     """The step's memory pattern with no arithmetic (lbm_pattern_probe) on an
     nx x ny grid: ping-pong (alternating buffers) or in place (even and odd
     launches alternating); GB/s at 448 B per node and launch, for each cache
@@ -701,6 +704,7 @@ def pattern_probe(nx, ny, inplace, launches=40):
             mode, fd, fs = 1 + (k & 1), f[0], f[0]
         else:
             mode, fd, fs = 0, f[(k + 1) & 1], f[k & 1]
+        mode += 3 if blocked else 0
         _lib.check(lib.lbm_pattern_probe(mode, pol, ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(fs.data_ptr()),
                                          ctypes.c_void_p(g[(k + 1) & 1].data_ptr()),
                                          ctypes.c_void_p(g[k & 1].data_ptr()), nx, ny,

@@ -247,7 +247,10 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_s
  * opposite.  mode 0 (ping-pong, f_dst != f_src): f_dst[i](x) =
  * f_src[i](x - c_i); mode 1 (in place, even step, f_dst == f_src):
  * f[48 - i](x) = f[i](x); mode 2 (in place, odd step, f_dst == f_src):
- * f[i](x + c_i) = f[48 - i](x - c_i).  Every mode copies g_src to g_dst
+ * f[i](x + c_i) = f[48 - i](x - c_i); modes 3, 4, 5: the same with f in
+ * 64-node blocks along x (value i of node (x, y) at
+ * ((y * nx / 64 + x / 64) * 49 + i) * 64 + x % 64; nx a multiple of 64).
+ * Every mode copies g_src to g_dst
  * (distinct).  policy 0: default cache policy; 1: non-temporal loads of f;
  * 2: non-temporal loads and stores of f; 3: default policy for f,
  * non-temporal loads and stores of g.  448 B of memory traffic per node,

@@ -36,14 +36,20 @@ __global__ void __launch_bounds__(256) k_stream_copy(const f32x4 *__restrict__ s
 // POL 0: default cache policy; 1: non-temporal loads of f; 2: non-temporal
 // loads and stores of f; 3: default for f, non-temporal loads and stores of
 // g.  Otherwise g rows are copied with the default policy.
-template <int MODE, int POL>
+// BLK: f in 64-node blocks along x, population-major inside (value i of
+// node (x, y) at ((y * nx / 64 + x / 64) * 49 + i) * 64 + x % 64; nx a
+// multiple of 64) instead of rows [49][nx * ny].
+template <int MODE, int POL, bool BLK>
 __global__ void __launch_bounds__(256) k_pattern_2d(const float *fs, float *fd, const float *__restrict__ gs,
                                                    float *__restrict__ gd, int nx, int ny) {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
     if (x >= nx) return;
     const size_t N = (size_t)nx * ny;
     auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
-    auto at = [&](int i, int xx, int yy) { return (size_t)i * N + (size_t)wrap(yy, ny) * nx + wrap(xx, nx); };
+    auto at = [&](int i, int xx, int yy) {
+        const size_t xw = (size_t)wrap(xx, nx), yw = (size_t)wrap(yy, ny);
+        return BLK ? ((yw * (size_t)(nx / 64) + xw / 64) * 49 + i) * 64 + xw % 64 : (size_t)i * N + yw * nx + xw;
+    };
     float v[49];
 #pragma unroll
     for (int i = 0; i < 49; ++i) {
@@ -70,17 +76,17 @@ __global__ void __launch_bounds__(256) k_pattern_2d(const float *fs, float *fd, 
     }
 }
 
-template <int MODE>
+template <int MODE, bool BLK>
 static void launch_pattern(int pol, dim3 grid, hipStream_t s, const float *fs, float *fd, const float *gs, float *gd,
                            int nx, int ny) {
     if (pol == 0)
-        hipLaunchKernelGGL((k_pattern_2d<MODE, 0>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 0, BLK>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
     else if (pol == 1)
-        hipLaunchKernelGGL((k_pattern_2d<MODE, 1>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 1, BLK>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
     else if (pol == 2)
-        hipLaunchKernelGGL((k_pattern_2d<MODE, 2>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 2, BLK>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
     else
-        hipLaunchKernelGGL((k_pattern_2d<MODE, 3>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
+        hipLaunchKernelGGL((k_pattern_2d<MODE, 3, BLK>), grid, dim3(256), 0, s, fs, fd, gs, gd, nx, ny);
 }
 
 }  // namespace lbmx
@@ -92,11 +98,16 @@ extern "C" lbm_status lbm_pattern_probe(int32_t mode, int32_t policy, float *f_d
         lbmx::set_error("lbm_pattern_probe: NULL buffer");
         return LBM_EINVAL;
     }
-    if (mode < 0 || mode > 2 || policy < 0 || policy > 3) {
-        lbmx::set_error("lbm_pattern_probe: mode must be 0, 1 or 2 and policy 0 to 3");
+    if (mode < 0 || mode > 5 || policy < 0 || policy > 3) {
+        lbmx::set_error("lbm_pattern_probe: mode must be 0 to 5 and policy 0 to 3");
         return LBM_EINVAL;
     }
-    if ((mode == 0) == (f_dst == f_src) || g_dst == g_src) {
+    const bool blk = mode >= 3;
+    if (blk && nx % 64) {
+        lbmx::set_error("lbm_pattern_probe: the blocked modes need nx a multiple of 64");
+        return LBM_EINVAL;
+    }
+    if ((mode % 3 == 0) == (f_dst == f_src) || g_dst == g_src) {
         lbmx::set_error("lbm_pattern_probe: mode 0 needs distinct f buffers, modes 1 and 2 one buffer; "
                         "g buffers must be distinct");
         return LBM_EINVAL;
@@ -108,11 +119,17 @@ extern "C" lbm_status lbm_pattern_probe(int32_t mode, int32_t policy, float *f_d
     const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)ny);
     const hipStream_t s = (hipStream_t)hip_stream;
     if (mode == 0)
-        lbmx::launch_pattern<0>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+        lbmx::launch_pattern<0, false>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
     else if (mode == 1)
-        lbmx::launch_pattern<1>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+        lbmx::launch_pattern<1, false>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+    else if (mode == 2)
+        lbmx::launch_pattern<2, false>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+    else if (mode == 3)
+        lbmx::launch_pattern<0, true>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+    else if (mode == 4)
+        lbmx::launch_pattern<1, true>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
     else
-        lbmx::launch_pattern<2>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
+        lbmx::launch_pattern<2, true>(policy, grid, s, f_src, f_dst, g_src, g_dst, nx, ny);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         lbmx::set_error((std::string("lbm_pattern_probe: ") + hipGetErrorString(e)).c_str());

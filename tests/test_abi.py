@@ -242,7 +242,9 @@ def test_pattern_probe_rejects_bad_arguments(lib):
     assert L.lbm_pattern_probe(0, 0, a, a, c, d, 64, 64, None) == lib.LBM_EINVAL   # ping-pong needs two f
     assert L.lbm_pattern_probe(1, 0, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL   # in place needs one f
     assert L.lbm_pattern_probe(2, 0, a, a, c, c, 64, 64, None) == lib.LBM_EINVAL   # g distinct
-    assert L.lbm_pattern_probe(3, 0, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe(6, 0, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe(3, 0, a, b, c, d, 96, 64, None) == lib.LBM_EINVAL  # blocked: nx % 64
+    assert L.lbm_pattern_probe(4, 0, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL
     assert L.lbm_pattern_probe(0, 4, a, b, c, d, 64, 64, None) == lib.LBM_EINVAL
     assert L.lbm_pattern_probe(0, 0, a, b, c, d, 3, 64, None) == lib.LBM_EINVAL
     assert L.lbm_pattern_probe(0, 0, a, b, c, d, 64, 70000, None) == lib.LBM_EINVAL

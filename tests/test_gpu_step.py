@@ -435,23 +435,29 @@ def test_stream_copy(torch_cuda):
     assert torch.equal(dst, src)
 
 
-@pytest.mark.parametrize("mode,policy", [(0, 0), (0, 1), (0, 2), (1, 1), (2, 2), (1, 3), (2, 3)])
+@pytest.mark.parametrize("mode,policy", [(0, 0), (0, 1), (0, 2), (1, 1), (2, 2), (1, 3), (2, 3),
+                                         (3, 1), (4, 0), (5, 3)])
 def test_pattern_probe_moves_what_it_states(torch_cuda, mode, policy):
-    """The step's memory-pattern probe on a ragged 300 x 7 grid: ping-pong
-    shifts row i by c_i = (i % 7 - 3, i / 7 - 3) periodically; the in-place
-    even step swaps rows i and 48 - i; the odd step stores row 48 - i at
-    x - c_i into row i at x + c_i; g is copied."""
+    """The step's memory-pattern probe on a ragged 300 x 7 grid (320 x 7 in
+    the blocked modes): ping-pong shifts row i by c_i = (i % 7 - 3, i / 7 - 3)
+    periodically; the in-place even step swaps rows i and 48 - i; the odd
+    step stores row 48 - i at x - c_i into row i at x + c_i; g is copied.
+    Modes 3-5 do the same on f in 64-node blocks."""
     import ctypes
     import torch
     from paper_1606_06107_amd import _lib
     announce(f"pattern probe mode {mode} policy {policy}")
     lib = _lib.load()
-    nx, ny = 300, 7
+    blk = mode >= 3
+    nx, ny = (320 if blk else 300), 7
     g = torch.Generator().manual_seed(5)
     f0 = torch.randn(49, ny, nx, generator=g)
     g0 = torch.randn(7, ny, nx, generator=g)
-    fs = f0.cuda()
-    fd = torch.full_like(fs, float("nan")) if mode == 0 else fs
+
+    def order(a):  # [49][ny][nx] -> the layout the probe runs on
+        return a.reshape(49, ny, nx // 64, 64).permute(1, 2, 0, 3).contiguous() if blk else a
+    fs = order(f0).cuda()
+    fd = torch.full_like(fs, float("nan")) if mode % 3 == 0 else fs
     gs, gd = g0.cuda(), torch.full((7, ny, nx), float("nan"), device="cuda")
     _lib.check(lib.lbm_pattern_probe(mode, policy, ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(fs.data_ptr()),
                                      ctypes.c_void_p(gd.data_ptr()), ctypes.c_void_p(gs.data_ptr()), nx, ny,
@@ -460,13 +466,13 @@ def test_pattern_probe_moves_what_it_states(torch_cuda, mode, policy):
     want = torch.empty_like(f0)
     for i in range(49):
         cx, cy = i % 7 - 3, i // 7 - 3
-        if mode == 0:
+        if mode % 3 == 0:
             want[i] = torch.roll(f0[i], shifts=(cy, cx), dims=(0, 1))
-        elif mode == 1:
+        elif mode % 3 == 1:
             want[48 - i] = f0[i]
         else:
             want[i] = torch.roll(f0[48 - i], shifts=(2 * cy, 2 * cx), dims=(0, 1))
-    assert torch.equal(fd.cpu(), want)
+    assert torch.equal(fd.cpu(), order(want))
     assert torch.equal(gd.cpu(), g0)
 
 
