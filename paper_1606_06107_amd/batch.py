@@ -65,9 +65,11 @@ class Batch:
         return ctypes.c_void_p(self.stream.cuda_stream)
 
     def init(self, rho, u, T):
-        """Equilibrium initial state from packed FP64 fields (length total)."""
-        self._fields = [torch.as_tensor(np.asarray(a, dtype=np.float64).reshape(-1)).to(self.device)
+        """Equilibrium initial state from packed FP64 fields (length total;
+        numpy arrays or torch tensors, device tensors used in place)."""
+        self._fields = [torch.as_tensor(a, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
                         for a in (rho, u, T)]
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))  # conversions above ran there
         r, u_, T_ = self._fields
         assert r.numel() == self.total and u_.numel() == self.total and T_.numel() == self.total
         L.check(self.lib.lbm_batch_init(ctypes.byref(self.desc), _p(r), _p(u_), _p(T_), self._s()))

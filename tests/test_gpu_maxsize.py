@@ -73,3 +73,63 @@ def test_largest_1d_tube_matches_oracle_windows(dtype_name):
         assert err <= TOL[dtype_name], (a, b, err)
     del sim, r_d, u_d, T_d
     torch.cuda.empty_cache()
+
+
+def _windows(lo_tube, n, a, b):
+    """Oracle range [lo, hi) around window [a, b) of an n-node tube and the
+    slice of it (relative to lo) that the range's artificial edges cannot
+    reach within STEPS steps."""
+    lo, hi = max(0, a - MARGIN), min(n, b + MARGIN)
+    keep_lo = a - lo if lo == 0 else max(a - lo, MARGIN)
+    keep_hi = (b - lo) if hi == n else min(b - lo, hi - lo - MARGIN)
+    return lo, hi, slice(keep_lo, keep_hi)
+
+
+def test_batch_beyond_2_30_nodes_matches_oracle_windows():
+    """Three 400 M-node tubes and a 1000-node one (1.2e9 nodes, FP32 rows of
+    4.8 GB) in one persistent launch, per-tube n and tau, 4 steps: oracle
+    windows at each long tube's start, middle and end, and the short tube
+    whole."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1606_06107_amd import Batch
+    lengths = np.array([400_000_000, 400_000_000, 400_000_003, 1000], dtype=np.int64)
+    n_rot = np.array([2.0, 3.0, 1.5, 4.0])
+    tau = np.array([0.8, 0.9, 0.7, 1.0])
+    total = int(lengths.sum())
+    free, _ = torch.cuda.mem_get_info()
+    need = 4 * 7 * total * 4 + 6 * 8 * total
+    if free < need * 1.15:
+        pytest.skip(f"needs {need / 1e9:.0f} GB of device memory, {free / 1e9:.0f} GB free")
+    announce(f"batch of {len(lengths)} tubes, {total} nodes, FP32 x {STEPS} steps")
+    x = torch.arange(total, dtype=torch.float64, device="cuda")
+    rho, u, T = _fields(x, torch.remainder, torch.sin, torch.cos)
+    del x
+    b = Batch(lengths, n_rot, tau, np.full(len(lengths), STEPS), dtype=torch.float32).init(rho, u, T)
+    del rho, u, T
+    b.step()
+    st = b.status.cpu().numpy()
+    assert (st == 0).all(), st
+    r_d, u_d, T_d = b.moments()
+    torch.cuda.synchronize()
+    off = b.offsets_h
+    for i, n in enumerate(lengths):
+        n = int(n)
+        wins = [(0, n)] if n <= 1000 else [(0, 300), (n // 2 - 150, n // 2 + 150), (n - 300, n)]
+        for a, bb in wins:
+            lo, hi, sl = _windows(0, n, a, bb)
+            xs = np.arange(off[i] + lo, off[i] + hi, dtype=np.float64)
+            G = oracle.Grid(oracle.D1Q7, (hi - lo,), bc=(oracle.OPEN,), n_rot=float(n_rot[i]), tau=float(tau[i]))
+            r0, u0, T0 = _fields(xs)
+            f, g = G.init_eq(r0, u0.reshape(1, -1), T0)
+            G.step(f, g, STEPS)
+            orr, oru, orT = G.moments(f, g)[:3]
+            gr = [t[off[i] + lo:off[i] + hi].cpu().numpy()[sl] for t in (r_d, u_d, T_d)]
+            err = max(float(np.abs(gr[0] - orr[sl]).max()), float(np.abs(gr[1] - oru[0][sl]).max()),
+                      float(np.abs(gr[2] - orT[sl]).max()))
+            print(f"tube {i} window [{a}, {bb}): L-inf {err:.2e}", flush=True)
+            assert err <= TOL["float32"], (i, a, bb, err)
+    b.release()
+    del b, r_d, u_d, T_d
+    torch.cuda.empty_cache()
