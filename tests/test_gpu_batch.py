@@ -219,3 +219,39 @@ def test_batch_substeps_equal_per_step_path_and_noalloc(torch_cuda):
     ref = np.stack([r1.cpu().numpy(), u1[0].cpu().numpy(), T1.cpu().numpy()])
     assert np.abs(outs[0] - ref).max() <= 1e-12 * np.abs(ref).max()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_degenerate_calls(torch_cuda):
+    """Zero steps change nothing (Sim.step(0); a batch whose tubes all have
+    0 steps: status 0, 0 steps done, populations bitwise unchanged), and the
+    shortest tube the batch accepts (4 nodes) matches the oracle."""
+    import torch
+    from paper_1606_06107_amd import Batch, Sim
+    from gpu_helpers import smooth_fields
+    announce("degenerate calls")
+    fields = smooth_fields((20, 12), 3)
+    sim = Sim((20, 12), n_rot=2.0, tau=0.8, dtype=torch.float32).init(*fields)
+    sim.step(3)
+    f0, g0 = (t.clone() for t in sim.populations())
+    t0 = sim.t
+    sim.step(0)
+    f1, g1 = sim.populations()
+    assert sim.t == t0
+    assert torch.equal(f0, f1) and torch.equal(g0, g1)
+
+    lengths = [4, 9, 300]
+    n_rot, tau, _, rho, u, T, _ = _mild_batch(7, lengths)
+    b = Batch(lengths, n_rot, tau, np.zeros(3, dtype=np.int64), dtype=torch.float64).init(rho, u, T)
+    fb, gb = b.f[0].clone(), b.g[0].clone()
+    b.step()
+    torch.cuda.synchronize()
+    assert (b.status.cpu().numpy() == 0).all() and (b.steps_done.cpu().numpy() == 0).all()
+    assert torch.equal(b.f[0], fb) and torch.equal(b.g[0], gb)
+
+    n_rot, tau, _, rho, u, T, fl = _mild_batch(8, [4])
+    b = Batch([4], n_rot, tau, [30], dtype=torch.float64).init(rho, u, T).step()
+    want = _oracle_tube(fl[0], float(n_rot[0]), float(tau[0]), 30)
+    got = [t.cpu().numpy() for t in b.moments()]
+    assert (b.status.cpu().numpy() == 0).all()
+    for k in range(3):
+        assert np.abs(got[k] - np.asarray(want[k]).reshape(-1)).max() <= 1e-12 * max(1.0, np.abs(want[k]).max())
