@@ -507,6 +507,7 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
     const int r0 = 32 * w;
     const size_t BL = (size_t)a.B * a.L;
     auto in_tube = [&](int r) { return t0 + r >= 0 && t0 + r < a.T; };
+    const bool full = t0 >= 0 && t0 + FR <= a.T;  // every row of the tile inside the tube
 
     // Embedding H0 = X We^T + be; rows outside the tube are zero (padding).
     {
@@ -547,6 +548,7 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
 #pragma unroll
             for (int q = 0; q < TAPS; ++q) kc[q] = blk[B_KC + c * TAPS + q];
             const float bc = blk[B_BC + c];
+            const float kc2 = kc[2] + 1.0f;  // the residual folded into the centre tap
             float win[36];
 #pragma unroll
             for (int m = 0; m < 36; ++m) {
@@ -554,9 +556,10 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
             }
 #pragma unroll
             for (int m = 0; m < 32; ++m) {
-                float v = win[m + 2] + bc;
+                float v = fmaf(kc2, win[m + 2], bc);
 #pragma unroll
-                for (int q = 0; q < TAPS; ++q) v += kc[q] * win[m + q];
+                for (int q = 0; q < TAPS; ++q)
+                    if (q != 2) v = fmaf(kc[q], win[m + q], v);
                 hc[m] = v;
             }
         }
@@ -570,8 +573,10 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
         for (int s = 0; s < 4; ++s) hb[s] = frag_from_f32(&Hf[(r0 + n32) * HS + 16 * s + 8 * hl]);
         f32x16 acc2[2];
 #pragma unroll
-        for (int ot = 0; ot < 2; ++ot)
-            for (int i = 0; i < 16; ++i) acc2[ot][i] = 0.0f;
+        for (int ot = 0; ot < 2; ++ot) {
+            const float b2 = blk[B_B2 + 32 * ot + n32];
+            for (int i = 0; i < 16; ++i) acc2[ot][i] = b2;
+        }
 #pragma unroll
         for (int h = 0; h < 4; ++h) {  // 32-wide hidden tiles
             // The tile's eight weight fragments, issued together.
@@ -595,18 +600,23 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
                     acc2[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, w2[2 * cc + ot], acc2[ot], 0, 0, 0);
             }
         }
-        // H' = Hc + A1 W2^T + b2 on the wave's rows (zero outside the tube).
+        // H' = Hc + (b2 + A1 W2^T) on the wave's rows (zero outside the tube).
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot) {
             const int ch = 32 * ot + n32;
-            const float b2 = blk[B_B2 + ch];
             float hv[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) hv[i] = Hf[(r0 + 8 * (i >> 2) + 4 * hl + (i & 3)) * HS + ch];
+            if (full) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
-                Hf[r * HS + ch] = in_tube(r) ? hv[i] + acc2[ot][i] + b2 : 0.0f;
+                for (int i = 0; i < 16; ++i)
+                    Hf[(r0 + 8 * (i >> 2) + 4 * hl + (i & 3)) * HS + ch] = hv[i] + acc2[ot][i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
+                    Hf[r * HS + ch] = in_tube(r) ? hv[i] + acc2[ot][i] : 0.0f;
+                }
             }
         }
     }
