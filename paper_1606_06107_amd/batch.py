@@ -84,11 +84,18 @@ class Batch:
             self.nsteps.copy_(torch.as_tensor(np.asarray(nsteps, dtype=np.int64)))
         cur.wait_stream(self.stream)
 
-    def step(self, stream=None):
+    def step(self, stream=None, chunk=None):
         """Advance every tube i by nsteps[i] steps (one persistent launch), on
-        the batch's stream or on `stream`."""
+        the batch's stream or on `stream`; `chunk` overrides the batch's chunk
+        size for this call (0: the library's default shape)."""
         s = self._s() if stream is None else ctypes.c_void_p(stream.cuda_stream)
-        L.check(self.lib.lbm_batch_step(ctypes.byref(self.desc), s))
+        keep = self.desc.chunk
+        if chunk is not None:
+            self.desc.chunk = int(chunk)
+        try:
+            L.check(self.lib.lbm_batch_step(ctypes.byref(self.desc), s))
+        finally:
+            self.desc.chunk = keep
         return self
 
     def step_noalloc(self):
