@@ -142,9 +142,9 @@ def _events(stream):
 
 
 def extra_tube_1d():
-    """The 1-D workloads, FP64, 1000 nodes x 1000 steps, each as one HIP graph:
-    the classic Sod tube (rotational advection in 4 sub-steps), and the
-    Sec. VI tube's states with the update as written -- the latter also as a
+    """The 1-D workloads, FP64, 1000 nodes x 1000 steps: the classic Sod tube
+    (rotational advection in 4 sub-steps) and the Sec. VI tube's states with
+    the update as written, each as one HIP graph of per-step kernels and as a
     batch of one (the whole time loop on chip in one launch)."""
     import numpy as np
     import torch
@@ -163,40 +163,44 @@ def extra_tube_1d():
         sim.step(w.steps)
         b.record(sim.stream)
         torch.cuda.synchronize()
-        ms = a.elapsed_time(b)
-        return sim, ms
+        return sim, a.elapsed_time(b)
 
-    w = workloads.tube_1d()
-    sim, ms_sod = timed_sim(w)
-    r0, _, T0, _ = sim.moments()
-    sod_ok = bool(torch.isfinite(T0).all().item() and (r0.min() > 0).item() and (T0.min() > 0).item())
-    w = workloads.paper_tube_1d()
-    sim, ms = timed_sim(w)
-    r1, u1, T1, _ = sim.moments()
-    rho0, u0, T0_ = w.fields()
-    bt = Batch([w.N], [w.n_rot], [w.tau], [w.steps], dtype=torch.float64)
-    bt.init(rho0, np.asarray(u0).reshape(-1), T0_).step()  # capture + warm
-    bt.init(rho0, np.asarray(u0).reshape(-1), T0_)
-    a, b = _events(bt.stream)
-    torch.cuda.synchronize()
-    a.record(bt.stream)
-    bt.step()
-    b.record(bt.stream)
-    torch.cuda.synchronize()
-    ms_b = a.elapsed_time(b)
-    r2, u2, T2 = bt.moments()
-    diff = max(float((r1 - r2).abs().max()), float((u1.reshape(-1) - u2).abs().max()), float((T1 - T2).abs().max()))
-    return {"classic_sod": {"workload": "1-D classic Sod (1,0,1)|(0.125,0,0.1), 1000 nodes, n=4, tau=1, "
-                                        "rotational advection in 4 sub-steps, FP64, 1000 steps",
-                            "ms_total": round(ms_sod, 3), "us_per_step": round(1000 * ms_sod / 1000, 2),
-                            "MLUPS": round(1000 * 1000 / ms_sod / 1e3, 1), "finite_positive": sod_ok},
-            "paper_tube": {"workload": "1-D tube (4,0,4)|(1,0,1), 1000 nodes, n=4, tau=0.8, FP64, 1000 steps",
-                           "per_step_kernels": {"ms_total": round(ms, 3), "us_per_step": round(1000 * ms / w.steps, 2),
-                                                "MLUPS": round(w.N * w.steps / ms / 1e3, 1)},
-                           "on_chip_batch_of_one": {"ms_total": round(ms_b, 3),
-                                                    "us_per_step": round(1000 * ms_b / w.steps, 3),
-                                                    "MLUPS": round(w.N * w.steps / ms_b / 1e3, 1),
-                                                    "max_abs_diff_vs_per_step": diff}}}
+    def timed_batch(w):
+        rho0, u0, T0_ = w.fields()
+        bt = Batch([w.N], [w.n_rot], [w.tau], [w.steps], dtype=torch.float64, g_substeps=w.g_substeps)
+        bt.init(rho0, np.asarray(u0).reshape(-1), T0_).step()  # capture + warm
+        bt.init(rho0, np.asarray(u0).reshape(-1), T0_)
+        a, b = _events(bt.stream)
+        torch.cuda.synchronize()
+        a.record(bt.stream)
+        bt.step()
+        b.record(bt.stream)
+        torch.cuda.synchronize()
+        return bt, a.elapsed_time(b)
+
+    out = {}
+    for name, w, what in (("classic_sod", workloads.tube_1d(),
+                           "1-D classic Sod (1,0,1)|(0.125,0,0.1), 1000 nodes, n=4, tau=1, rotational advection "
+                           "in 4 sub-steps, FP64, 1000 steps"),
+                          ("paper_tube", workloads.paper_tube_1d(),
+                           "1-D tube (4,0,4)|(1,0,1), 1000 nodes, n=4, tau=0.8, FP64, 1000 steps")):
+        sim, ms = timed_sim(w)
+        r1, u1, T1, _ = sim.moments()
+        bt, ms_b = timed_batch(w)
+        r2, u2, T2 = bt.moments()
+        ok = bool(torch.isfinite(T1).all().item() and (r1.min() > 0).item() and (T1.min() > 0).item())
+        diff = max(float((r1 - r2).abs().max()), float((u1.reshape(-1) - u2).abs().max()),
+                   float((T1 - T2).abs().max()))
+        out[name] = {"workload": what, "finite_positive": ok,
+                     "per_step_kernels": {"ms_total": round(ms, 3), "us_per_step": round(1000 * ms / w.steps, 2),
+                                          "MLUPS": round(w.N * w.steps / ms / 1e3, 1)},
+                     "on_chip_batch_of_one": {"ms_total": round(ms_b, 3),
+                                              "us_per_step": round(1000 * ms_b / w.steps, 3),
+                                              "MLUPS": round(w.N * w.steps / ms_b / 1e3, 1),
+                                              "max_abs_diff_vs_per_step": diff}}
+        bt.release()
+        del sim, bt
+    return out
 
 
 def extra_3d(steps=10):
