@@ -355,9 +355,10 @@ lbm_status lbm_batch_moments(const lbm_batch_desc *desc, double *rho, double *u,
 /* ------------------------------------------------------------------------ */
 /* Learned surrogate of the batched tubes: a 1-D neural operator that maps   */
 /* (rho, u, T, gamma) of a tube to (rho, u, T) k = 16 lattice steps later.   */
-/* The plain scheme above generates its training data, judges its error and  */
-/* replaces it wherever a conservation/admissibility check fails.  The paper */
-/* has no learned component; only the fallback and the judge are its method. */
+/* The plain scheme above generates its training data, is the reference its */
+/* error is measured against, and replaces it wherever a conservation or    */
+/* admissibility check fails.  The paper has no learned component; only the */
+/* fallback and the error reference are its method.                         */
 /*                                                                          */
 /* Network (tokens = patches of 4 nodes, C = 64 channels, 4 blocks):         */
 /*   X  [M][16]  features (rho-0.5)/0.5, u/0.5, (T-1)/0.5, (gamma-1.4)/0.3   */

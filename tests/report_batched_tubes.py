@@ -17,10 +17,10 @@ sub-steps.
 Not collected by pytest (a GPU report, not a test).  Usage, from the
 repository root on a GPU machine:
 
-    python tests/report_batched_tubes.py gpurun_out/batched_tubes_4096.md
+    python tests/report_batched_tubes.py out/batched_tubes_4096.md
 
-The per-instance table of the stable tubes goes to the .csv beside the
-given path's name under gpurun_out/ (it is too long for the summary)."""
+The per-instance table of the stable tubes goes to the .csv of the same
+name beside the given path (it is too long for the summary)."""
 from __future__ import annotations
 
 import os
@@ -269,10 +269,10 @@ def main(out_md):
     for m, n_ok, resc, lost, p50, p90, n32, ms_m, work_m in subrows:
         lines.append(f"| {m} | {n_ok} | {resc} | {lost} | " + " / ".join(f"{v:.2e}" for v in p50) + " | "
                      + " / ".join(f"{v:.2e}" for v in p90) + f" | {n32} | {ms_m:.2f} | {work_m / ms_m / 1e3:,.0f} |")
+    os.makedirs(os.path.dirname(os.path.join(ROOT, out_md)), exist_ok=True)
     with open(os.path.join(ROOT, out_md), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    csv = os.path.join(ROOT, "gpurun_out", os.path.splitext(os.path.basename(out_md))[0] + ".csv")
+    csv = os.path.splitext(os.path.join(ROOT, out_md))[0] + ".csv"
     header = ("tube,L,gamma,tau,pressure_ratio,density_ratio,steps,l1_f32_f64_rho,l1_f32_f64_u,l1_f32_f64_T,"
               "l1_exact_rho,l1_exact_u,l1_exact_p,l1_exact_T")
     np.savetxt(csv, rows, delimiter=",", header=header, comments="",
