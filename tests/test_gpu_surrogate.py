@@ -392,3 +392,61 @@ def test_forward_active_mask(torch_cuda):
     got = sur.forward(xd, gd, y, active=active).cpu().numpy()
     assert np.array_equal(got[:, [0, 2]], full[:, [0, 2]])
     assert np.all(got[:, 1] == 7.0)
+
+
+def test_trained_network_gains_over_the_plain_scheme(torch_cuda):
+    """What training buys: a network trained briefly on the GPU by the
+    library's own kernels (stable 4096-node tubes of the batched recipe,
+    seed 0; 15000 Adam steps) advances 256 held-out tubes (seed 10^6) by 256
+    steps -- the first 16 by the plain scheme, then 15 surrogate calls with
+    the admission check -- (a) close to the plain scheme's result, where the
+    untrained network (the identity map) is not, and (b) in less time than
+    the plain scheme's 256 steps of the same tubes."""
+    import torch
+    from paper_1606_06107_amd import Batch, Surrogate
+    from paper_1606_06107_amd import surrogate as SG
+    announce("trained surrogate vs plain scheme (256 tubes x 256 steps)")
+
+    def l1(p, q):
+        return (torch.abs(p - q).sum(-1) / torch.abs(q).sum(-1).clamp_min(1e-300)).mean(1).cpu().numpy()
+
+    bt = SG.stable_tubes(4096, seed=0)
+    x, tg, gm = SG.make_pairs(bt, pairs_per_tube=16, seed=1, start="zero")
+    sur = Surrogate(32, 4096)
+    sur.set_params(SG.init_params(0))
+    SG.train(sur, x, tg, gm, steps=15000, lr=2e-3)
+    del x, tg
+    te = SG.stable_tubes(4096, seed=10 ** 6)
+    te = te.subset(np.arange(256))
+    B = te.num
+    x0 = torch.as_tensor(np.stack([te.rho, te.u[0], te.T]).reshape(3, B, 4096), device="cuda")
+    gamma = torch.as_tensor(te.gamma, device="cuda")
+    plain = Batch(te.lengths, te.n_rot, te.tau, np.full(B, 256), dtype=torch.float32)
+    fb = Batch(te.lengths, te.n_rot, te.tau, np.zeros(B, dtype=np.int64), dtype=torch.float32, chunk=1024)
+    trained = sur.shape_like(B)
+    identity = Surrogate(B, 4096)
+    identity.set_params(np.zeros(SG.NPARAMS))
+
+    def timed(fn, setup=lambda: None):
+        best, out = None, None
+        for _ in range(3):
+            setup()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(trained.stream)
+            out = fn()
+            b.record(trained.stream)
+            torch.cuda.synchronize()
+            best = a.elapsed_time(b) if best is None else min(best, a.elapsed_time(b))
+        return best, out
+
+    t_lbm, _ = timed(lambda: plain.step(), setup=lambda: plain.init(te.rho, te.u[0], te.T))
+    ref = SG.fields_of(plain)
+    t_sur, (xr, acc) = timed(lambda: SG.rollout(trained, x0, gamma, fb, 16, plain_calls=1, max_mach=4.0))
+    xi, _ = SG.rollout(identity, x0, gamma, fb, 16, fallback=False, plain_calls=1)
+    e_tr, e_id = l1(xr, ref), l1(xi, ref)
+    print(f"relative L1 (rho, u, T) trained {np.round(e_tr, 4)}, identity {np.round(e_id, 4)}; "
+          f"tube-calls by the surrogate {acc.cpu().tolist()}; time {t_sur:.2f} ms against {t_lbm:.2f} ms",
+          flush=True)
+    assert (e_tr < 0.1).all() and e_tr[1] < 0.1 * e_id[1]
+    assert t_sur < t_lbm
