@@ -499,6 +499,11 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
     // edge rows reads them unconditionally.
     __shared__ __attribute__((aligned(16))) float Hs[(FR + 4) * HS];
     float *const Hf = Hs + 2 * HS;
+    // Copies of each wave's first two and last two rows, the only rows its
+    // neighbours' convolution windows read, double-buffered by block parity:
+    // a wave may then overwrite its own rows without waiting for the
+    // neighbours' reads.
+    __shared__ __attribute__((aligned(16))) float Hh[2][FNW][4][HS];
     for (int e = threadIdx.x; e < 4 * HS; e += 64 * FNW) Hs[e < 2 * HS ? e : (FR + 2) * HS + e - 2 * HS] = 0.0f;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, n32 = l & 31, hl = l >> 5;
     const int b = blockIdx.x / a.ntile, tile = blockIdx.x % a.ntile;
@@ -508,6 +513,13 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
     const size_t BL = (size_t)a.B * a.L;
     auto in_tube = [&](int r) { return t0 + r >= 0 && t0 + r < a.T; };
     const bool full = t0 >= 0 && t0 + FR <= a.T;  // every row of the tile inside the tube
+    // Row r0 + 8 (i >> 2) + 4 hl + (i & 3) of an accumulator element i is a
+    // boundary row for i = 0, 1 (hl = 0: rows 0, 1) and i = 14, 15 (hl = 1:
+    // rows 30, 31); keep its copy in slot 0..3.
+    auto keep_edge = [&](int par, int i, int ch, float v) {
+        if (i < 2 && hl == 0) Hh[par][w][i][ch] = v;
+        if (i >= 14 && hl == 1) Hh[par][w][i - 12][ch] = v;
+    };
 
     // Embedding H0 = X We^T + be; rows outside the tube are zero (padding).
     {
@@ -531,7 +543,9 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
-                Hf[r * HS + ch] = in_tube(r) ? acc[i] + be : 0.0f;
+                const float v = in_tube(r) ? acc[i] + be : 0.0f;
+                Hf[r * HS + ch] = v;
+                keep_edge(0, i, ch, v);
             }
         }
     }
@@ -539,7 +553,8 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
     for (int k = 0; k < NB; ++k) {
         const float *blk = a.P + P_BLK + k * BLK;
         const __bf16 *qb = a.Q + Q_BLK + k * QBLK;
-        __syncthreads();  // H of every row written
+        __syncthreads();  // H of every row and its edge copies written
+        const int par = k & 1;
         // Depthwise convolution: lane = channel, the wave's 32 rows.
         float hc[32];
         {
@@ -550,10 +565,16 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
             const float bc = blk[B_BC + c];
             const float kc2 = kc[2] + 1.0f;  // the residual folded into the centre tap
             float win[36];
+            // rows r0-2, r0-1 and r0+32, r0+33 from the neighbours' edge
+            // copies (the zero rows at the tile's ends)
+            const float *lo = w == 0 ? Hf - 2 * HS : &Hh[par][w - 1][2][0];
+            const float *hi = w == FNW - 1 ? Hf + FR * HS : &Hh[par][w + 1][0][0];
+            win[0] = lo[c];
+            win[1] = lo[HS + c];
 #pragma unroll
-            for (int m = 0; m < 36; ++m) {
-                win[m] = Hf[(r0 + m - 2) * HS + c];
-            }
+            for (int m = 2; m < 34; ++m) win[m] = Hf[(r0 + m - 2) * HS + c];
+            win[34] = hi[c];
+            win[35] = hi[HS + c];
 #pragma unroll
             for (int m = 0; m < 32; ++m) {
                 float v = fmaf(kc2, win[m + 2], bc);
@@ -563,7 +584,7 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
                 hc[m] = v;
             }
         }
-        __syncthreads();  // every read of H done
+        // no other wave reads these rows in this block (edge copies above)
 #pragma unroll
         for (int m = 0; m < 32; ++m) Hf[(r0 + m) * HS + l] = hc[m];
         // MLP on the wave's rows.  B operand of Z1^T: token n32, channels
@@ -609,13 +630,18 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
             for (int i = 0; i < 16; ++i) hv[i] = Hf[(r0 + 8 * (i >> 2) + 4 * hl + (i & 3)) * HS + ch];
             if (full) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    Hf[(r0 + 8 * (i >> 2) + 4 * hl + (i & 3)) * HS + ch] = hv[i] + acc2[ot][i];
+                for (int i = 0; i < 16; ++i) {
+                    const float v = hv[i] + acc2[ot][i];
+                    Hf[(r0 + 8 * (i >> 2) + 4 * hl + (i & 3)) * HS + ch] = v;
+                    keep_edge(par ^ 1, i, ch, v);
+                }
             } else {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int r = r0 + 8 * (i >> 2) + 4 * hl + (i & 3);
-                    Hf[r * HS + ch] = in_tube(r) ? hv[i] + acc2[ot][i] : 0.0f;
+                    const float v = in_tube(r) ? hv[i] + acc2[ot][i] : 0.0f;
+                    Hf[r * HS + ch] = v;
+                    keep_edge(par ^ 1, i, ch, v);
                 }
             }
         }
