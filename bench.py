@@ -66,36 +66,51 @@ def _cpu_model():
     return f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, model {info.get('model', '?')})"
 
 
-def cpu_baseline(nx, ny, steps, threads, single=(512, 512, 30)):
+def cpu_baseline(nx, ny, steps, threads, single=(512, 512, 30), parity_steps=50):
     """The CPU oracle (plain C, FP64) on bounded samples of the same workload:
-    all of this process's host cores (at most `threads`), and one core."""
+    all of this process's host cores (at most `threads`), and one core.  The
+    all-core run also gives the FP32 GPU path's error against the oracle on
+    the benchmark grid: L-inf of rho, u, T after `parity_steps` steps."""
     import numpy as np
+    import torch
 
     import oracle
     import workloads
+    from paper_1606_06107_amd import Sim
 
-    def run(nx_, ny_, steps_, th):
+    def run(nx_, ny_, steps_, th, snap=0):
         used = oracle.set_threads(th)
         w = workloads.Periodic2D(nx=nx_, ny=ny_)
         rho, u, T = w.fields()
         G = oracle.Grid(oracle.D2Q49, (nx_, ny_), n_rot=w.n_rot, tau=w.tau)
         f, g = G.init_eq(rho, u, T)
-        G.step(f, g, 1)  # warm-up (page faults, thread start)
-        t0 = time.perf_counter()
-        G.step(f, g, steps_)
-        dt = time.perf_counter() - t0
+        G.step(f, g, 1)  # warm-up (page faults, thread start); step 1 of the trajectory
+        done, dt, moments = 1, 0.0, None
+        for seg in ([snap - 1, steps_ - snap + 1] if snap > 1 else [steps_]):
+            t0 = time.perf_counter()
+            G.step(f, g, seg)
+            dt += time.perf_counter() - t0
+            done += seg
+            if done == snap:
+                moments = G.moments(f, g)[:3]
         assert np.isfinite(f).all()
-        return used, nx_ * ny_ * steps_ / dt / 1e6, dt
+        return used, nx_ * ny_ * steps_ / dt / 1e6, dt, moments, w
 
-    used, mlups, dt = run(nx, ny, steps, threads)
+    used, mlups, dt, orc, w = run(nx, ny, steps, threads, snap=parity_steps)
+    sim = Sim((nx, ny), n_rot=w.n_rot, tau=w.tau, dtype=torch.float32).init(*w.fields())
+    sim.step(parity_steps)
+    gpu = [t.cpu().numpy() for t in sim.moments(totals=False)[:3]]
+    del sim
+    err = {k: float(np.abs(np.asarray(a) - np.asarray(b)).max()) for k, a, b in zip(("rho", "u", "T"), gpu, orc)}
     s_nx, s_ny, s_steps = single
-    _, mlups1, dt1 = run(s_nx, s_ny, s_steps, 1)
+    _, mlups1, dt1, _, _ = run(s_nx, s_ny, s_steps, 1)
     oracle.set_threads(threads)
     return {"value": round(mlups, 4), "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"{nx}x{ny} nodes x {steps} steps of the same 2-D workload, FP64, "
                       f"{used} threads, {dt:.1f} s wall",
             "single_core": {"value": round(mlups1, 4), "unit": "MLUPS",
                             "sample": f"{s_nx}x{s_ny} nodes x {s_steps} steps, 1 thread, {dt1:.1f} s wall"},
+            "fp32_gpu_vs_oracle_linf": {"steps": parity_steps, **{k: float(f"{v:.3g}") for k, v in err.items()}},
             "cpu_model": _cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
