@@ -352,9 +352,10 @@ def test_rollout_mixed_verdicts(torch_cuda):
 
 def test_rollout_plain_first_then_all_accepted(torch_cuda):
     """A plain first call (every tube's batch populations are then live)
-    followed by calls that every tube passes: the first accepted call resets
-    the live flags, and the result is the surrogate chained on the plain
-    scheme's first 16 steps, bitwise."""
+    followed by calls that every tube passes: the batch keeps the plain
+    call's populations (live flags stay set, for a later restart), and the
+    result is the surrogate chained on the plain scheme's first 16 steps,
+    bitwise."""
     announce("rollout plain first, then all accepted")
     import torch
     from paper_1606_06107_amd import Batch
@@ -368,13 +369,51 @@ def test_rollout_plain_first_then_all_accepted(torch_cuda):
     fb = Batch([L] * B, n_rot, [0.8] * B, np.zeros(B, dtype=np.int64), dtype=torch.float32)
     xr, acc = rollout(sur, x0, gd, fb, calls, tols=(1e300, 1e300, 1e300), plain_calls=1, max_mach=0.0)
     assert acc.cpu().tolist() == [0] + [B] * (calls - 1)
-    assert list(sur.valid.cpu().numpy()) == [0] * B
+    assert list(sur.valid.cpu().numpy()) == [1] * B
     plain = Batch([L] * B, n_rot, [0.8] * B, np.full(B, 16), dtype=torch.float32)
     plain.init(x[0].ravel(), x[1].ravel(), x[2].ravel()).step()
     ref = fields_of(plain)
     for _ in range(calls - 1):
         ref = sur.forward(ref, gd)
     assert np.array_equal(xr.cpu().numpy(), ref.cpu().numpy())
+
+
+def test_rollout_late_rejection_restarts_from_the_plain_calls(torch_cuda):
+    """A network whose only parameter is the head bias of the velocity
+    outputs adds 0.1 to u in every call; against a Mach envelope of 0.3 the
+    tube at rest passes two surrogate calls and fails the third, the tube in
+    motion at Mach 0.5 fails the first, the tube starting at u = -0.25 never
+    fails.  Both rejected tubes restart from the populations the batch kept
+    after the plain first call and end bitwise where the plain scheme's own
+    run does; the third is the surrogate chained on the plain call."""
+    announce("rollout: late rejection restarts from the plain call")
+    import torch
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd.surrogate import fields_of, rollout
+    L, calls = 512, 5
+    x, gamma = _mixed_tubes(L)
+    x[1, 2] = -0.25
+    B = x.shape[1]
+    n_rot = 2.0 / (gamma - 1.0) - 1.0
+    tau = [0.8] * B
+    d = {name: np.zeros(shape) for name, shape in S.layout()}
+    d["bh"][1::3] = 1.0  # outputs 3p + 1 (u of node 4t + p): +0.1 per call
+    sur = _gpu(torch, S.pack(d), B, L)
+    x0, gd = _dev(torch, x), _dev(torch, gamma)
+    fb = Batch([L] * B, n_rot, tau, np.zeros(B, dtype=np.int64), dtype=torch.float32)
+    xr, acc = rollout(sur, x0, gd, fb, calls, tols=(1e300, 1e300, 1e300), plain_calls=1, max_mach=0.3)
+    assert acc.cpu().tolist() == [0, 2, 2, 1, 1]
+    full = Batch([L] * B, n_rot, tau, np.full(B, 16 * calls), dtype=torch.float32)
+    full.init(x[0].ravel(), x[1].ravel(), x[2].ravel()).step()
+    ref_full = fields_of(full).cpu().numpy()
+    plain = Batch([L] * B, n_rot, tau, np.full(B, 16), dtype=torch.float32)
+    plain.init(x[0].ravel(), x[1].ravel(), x[2].ravel()).step()
+    ref = fields_of(plain)
+    for _ in range(calls - 1):
+        ref = sur.forward(ref, gd)
+    got, ref = xr.cpu().numpy(), ref.cpu().numpy()
+    assert np.array_equal(got[:, [0, 1]], ref_full[:, [0, 1]])
+    assert np.array_equal(got[:, 2], ref[:, 2])
 
 
 def test_forward_active_mask(torch_cuda):
