@@ -249,10 +249,51 @@ def extra_3d(steps=10):
     ms, ok = run(True)
     ms_plain, ok_plain = run(False)
     gbs = N * 2800 / (ms * 1e-3) / 1e9
+    probe = pattern_probe_3d(w.n, steps)
     return {"workload": "3-D 256^3 turbulence, D3Q343+D1Q7 FP32, gamma=1.4", "order": "blocked (64 nodes)",
             "ms_per_step": round(ms, 3), "MLUPS": round(N / ms / 1e3, 1), "GBps": round(gbs, 1),
             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "finite": ok and ok_plain,
-            "plain_order_ms_per_step": round(ms_plain, 3)}
+            "plain_order_ms_per_step": round(ms_plain, 3),
+            "pattern_probe_GBps_by_policy": probe, "frac_of_pattern_probe": round(gbs / max(probe.values()), 4)}
+
+
+def pattern_probe_3d(n, launches=10):
+    """The blocked 3-D step's memory pattern with no arithmetic
+    (lbm_pattern_probe_3d) on an n^3 grid, ping-pong; GB/s at 2800 B per node
+    and launch for each cache policy (default, non-temporal loads,
+    non-temporal loads and stores)."""
+    import ctypes
+
+    import torch
+
+    from paper_1606_06107_amd import _lib
+    lib = _lib.load()
+    N = n ** 3
+    f = [torch.zeros(343 * N, device="cuda") for _ in range(2)]
+    g = [torch.zeros(7 * N, device="cuda") for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def launch(k, pol):
+        _lib.check(lib.lbm_pattern_probe_3d(pol, ctypes.c_void_p(f[(k + 1) & 1].data_ptr()),
+                                            ctypes.c_void_p(f[k & 1].data_ptr()),
+                                            ctypes.c_void_p(g[(k + 1) & 1].data_ptr()),
+                                            ctypes.c_void_p(g[k & 1].data_ptr()), n, n, n,
+                                            ctypes.c_void_p(stream.cuda_stream)))
+    for pol, name in ((0, "default"), (1, "nt_loads"), (2, "nt_loads_stores")):
+        for k in range(2):
+            launch(k, pol)
+        a, b = _events(stream)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for k in range(launches):
+            launch(k, pol)
+        b.record(stream)
+        torch.cuda.synchronize()
+        out[name] = round(N * 2800 / (a.elapsed_time(b) / launches * 1e-3) / 1e9, 1)
+    del f, g
+    torch.cuda.empty_cache()
+    return out
 
 
 def extra_3d_full(steps=2000, every=100, tau=None, fp64_gamma=1.4, n=256):

@@ -259,6 +259,19 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_s
 lbm_status lbm_pattern_probe(int32_t mode, int32_t policy, float *f_dst, const float *f_src, float *g_dst,
                              const float *g_src, int32_t nx, int32_t ny, void *hip_stream);
 
+/* Memory pattern of the 3-D D3Q343 + D1Q7 FP32 step in the blocked order, no
+ * arithmetic, ping-pong, on an n0 x n1 x n2 periodic grid (n0 a multiple of
+ * 64, n1, n2 >= 4, n0 n1 n2 * 4 < 2^32): f [343][N] values in 64-node blocks
+ * (value i of node (x, y, z) at ((b * 343 + i) * 64 + x % 64), b = (z n1 +
+ * y) n0 / 64 + x / 64), f_dst[i](x) = f_src[i](x - c_i) with c_i =
+ * (i % 7 - 3, i / 7 % 7 - 3, i / 49 - 3); g [7][N] (x fastest) copied.  policy
+ * 0: default cache policy; 1: non-temporal loads of f; 2: non-temporal loads
+ * and stores of f.  2800 B of memory traffic per node, as the step.  Not
+ * part of the scheme: the bandwidth ceiling of that pattern.  Errors:
+ * LBM_EINVAL, LBM_ELAUNCH. */
+lbm_status lbm_pattern_probe_3d(int32_t policy, float *f_dst, const float *f_src, float *g_dst,
+                                const float *g_src, int32_t n0, int32_t n1, int32_t n2, void *hip_stream);
+
 /* Lattice constants the library computes with: Q, r, and (if not NULL) the
  * weights w[Q] and velocities c[Q][3] (integers) of the population slots in
  * storage order (populations[Q][N] of lbm_populations / lbm_init_populations;

@@ -67,6 +67,7 @@ SIGNATURES = {
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_stream_copy": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
     "lbm_pattern_probe": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp]),
+    "lbm_pattern_probe_3d": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_i32, c_vp]),
     "lbm_lattice_info": (c_i32, [c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_dbl), c_vp, c_vp]),
     "lbm_batch_workspace_bytes": (c_sz, [ctypes.POINTER(LbmBatchDesc)]),
     "lbm_batch_init": (c_i32, [ctypes.POINTER(LbmBatchDesc), c_vp, c_vp, c_vp, c_vp]),

@@ -249,3 +249,15 @@ def test_pattern_probe_rejects_bad_arguments(lib):
     assert L.lbm_pattern_probe(0, 0, a, b, c, d, 3, 64, None) == lib.LBM_EINVAL
     assert L.lbm_pattern_probe(0, 0, a, b, c, d, 64, 70000, None) == lib.LBM_EINVAL
     assert L.lbm_pattern_probe(0, 0, None, b, c, d, 64, 64, None) == lib.LBM_EINVAL
+
+
+def test_pattern_probe_3d_rejects_bad_arguments(lib):
+    L = lib.load()
+    a, b, c, d = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x4000))
+    assert L.lbm_pattern_probe_3d(0, a, a, c, d, 64, 8, 8, None) == lib.LBM_EINVAL    # f distinct
+    assert L.lbm_pattern_probe_3d(0, a, b, c, c, 64, 8, 8, None) == lib.LBM_EINVAL    # g distinct
+    assert L.lbm_pattern_probe_3d(3, a, b, c, d, 64, 8, 8, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe_3d(0, a, b, c, d, 96, 8, 8, None) == lib.LBM_EINVAL    # n0 % 64
+    assert L.lbm_pattern_probe_3d(0, a, b, c, d, 64, 3, 8, None) == lib.LBM_EINVAL
+    assert L.lbm_pattern_probe_3d(0, a, b, c, d, 1024, 1024, 1024, None) == lib.LBM_EINVAL  # 2^32 bytes
+    assert L.lbm_pattern_probe_3d(0, None, b, c, d, 64, 8, 8, None) == lib.LBM_EINVAL

@@ -476,6 +476,38 @@ def test_pattern_probe_moves_what_it_states(torch_cuda, mode, policy):
     assert torch.equal(gd.cpu(), g0)
 
 
+@pytest.mark.parametrize("policy", [0, 2])
+def test_pattern_probe_3d_moves_what_it_states(torch_cuda, policy):
+    """The blocked 3-D pattern probe on a 128 x 5 x 4 periodic grid: value i
+    moves by c_i = (i % 7 - 3, i / 7 % 7 - 3, i / 49 - 3) in the 64-node
+    blocked order; g is copied."""
+    import ctypes
+    import torch
+    from paper_1606_06107_amd import _lib
+    announce(f"3-D pattern probe policy {policy}")
+    lib = _lib.load()
+    n0, n1, n2 = 128, 5, 4
+    g = torch.Generator().manual_seed(6)
+    f0 = torch.randn(343, n2, n1, n0, generator=g)
+    g0 = torch.randn(7, n2, n1, n0, generator=g)
+
+    def blocked(a):  # [343][n2][n1][n0] -> blocks of 64 x-consecutive nodes, population-major
+        return a.reshape(343, n2, n1, n0 // 64, 64).permute(1, 2, 3, 0, 4).contiguous()
+    fs = blocked(f0).cuda()
+    fd = torch.full_like(fs, float("nan"))
+    gs, gd = g0.cuda(), torch.full((7, n2, n1, n0), float("nan"), device="cuda")
+    _lib.check(lib.lbm_pattern_probe_3d(policy, ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(fs.data_ptr()),
+                                        ctypes.c_void_p(gd.data_ptr()), ctypes.c_void_p(gs.data_ptr()), n0, n1, n2,
+                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    torch.cuda.synchronize()
+    want = torch.empty_like(f0)
+    for i in range(343):
+        cx, cy, cz = i % 7 - 3, i // 7 % 7 - 3, i // 49 - 3
+        want[i] = torch.roll(f0[i], shifts=(cz, cy, cx), dims=(0, 1, 2))
+    assert torch.equal(fd.cpu(), blocked(want))
+    assert torch.equal(gd.cpu(), g0)
+
+
 @pytest.mark.parametrize("case", ["2d-pingpong", "2d-inplace", "3d-blocked", "1d-fd", "2d-substeps", "d2q37"])
 def test_nan_poison_debug_mode(torch_cuda, case):
     """With every step's write-only destinations poisoned with NaN first
