@@ -31,6 +31,8 @@
 // rotational populations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <mutex>
 #include <string>
 #include <vector>
@@ -868,7 +870,10 @@ lbm_status plan(const lbm_batch_desc *d, Launch *L) {
     // advection sub-steps): chunk halos of hw nodes per step of a pass.
     const int m = d->g_substeps > 1 ? d->g_substeps : 1;
     const int hw = 2 * m > 3 ? 2 * m : 3;
-    int S = d->superstep ? d->superstep : 24;
+    // Default passes of 128 / hw steps, at most 24: the halo recomputation
+    // (2 hw S of C nodes) grows with m, the per-pass overhead with 1/S
+    // (measured on the 4096-tube workload: m = 1: 24, m = 4: 16, m = 8: 8).
+    int S = d->superstep ? d->superstep : std::max(4, std::min(24, 128 / hw));
     if (!d->superstep && C - 2 * hw * S < 64) S = (C - 64) / (2 * hw);
     if (S < 1 || C - 2 * hw * S < 64) return bfail(LBM_EINVAL, "superstep too large for the chunk");
     L->block = B;
