@@ -161,11 +161,20 @@ struct lbm_sim_s {
         hipGraphExec_t exec;
     };
     std::vector<Entry> cache;
+    // recorded on `stream` after every graph launch: a graph is destroyed
+    // only once its last launch (all run in stream order) has finished
+    hipEvent_t launched = nullptr;
 };
 
 namespace {
 
+// Wait for the handle's last graph launch before a graph is destroyed.
+void wait_launched(lbm_sim s) {
+    if (s->launched) hipEventSynchronize(s->launched);
+}
+
 void clear_cache(lbm_sim s) {
+    if (!s->cache.empty()) wait_launched(s);
     for (auto &e : s->cache) hipGraphExecDestroy(e.exec);
     s->cache.clear();
 }
@@ -395,6 +404,7 @@ lbm_status graph_for(lbm_sim s, int64_t nsteps, hipGraphExec_t *out) {
     hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     if (s->cache.size() >= 8) {
+        wait_launched(s);
         hipGraphExecDestroy(s->cache.front().exec);
         s->cache.erase(s->cache.begin());
     }
@@ -475,6 +485,9 @@ lbm_status lbm_step(lbm_sim s, int64_t nsteps) {
     if (st) return st;
     hipError_t e = hipGraphLaunch(exec, s->stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
+    if (!s->launched && hipEventCreateWithFlags(&s->launched, hipEventDisableTiming) != hipSuccess)
+        s->launched = nullptr;
+    if (s->launched) hipEventRecord(s->launched, s->stream);
     advance(s, nsteps);
     s->t += nsteps;
     return LBM_OK;
@@ -636,6 +649,7 @@ lbm_status lbm_destroy(lbm_sim s) {
     if (!s) return LBM_OK;
     clear_cache(s);
     if (s->capture) hipStreamDestroy(s->capture);
+    if (s->launched) hipEventDestroy(s->launched);
     delete s;
     return LBM_OK;
 }

@@ -916,7 +916,16 @@ struct GraphEntry {
     int dev;
     lbm_batch_desc d;
     hipGraphExec_t exec;
+    hipEvent_t launched;  // recorded after every launch; waited for before the graph is destroyed
 };
+
+void destroy_entry(GraphEntry &en) {
+    if (en.launched) {
+        hipEventSynchronize(en.launched);
+        hipEventDestroy(en.launched);
+    }
+    hipGraphExecDestroy(en.exec);
+}
 constexpr size_t kGraphCap = 16;
 std::mutex g_mu;
 std::vector<GraphEntry> g_cache;
@@ -1042,6 +1051,7 @@ lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream) {
         if (en.dev == dev && same_desc(en.d, *desc)) {
             hipError_t e = hipGraphLaunch(en.exec, s);
             if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
+            if (en.launched) hipEventRecord(en.launched, s);
             return LBM_OK;
         }
     // record the order + persistent kernels once on a private stream
@@ -1065,12 +1075,15 @@ lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream) {
     hipGraphDestroy(graph);
     if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph instantiate: ") + hipGetErrorString(e));
     if (g_cache.size() >= kGraphCap) {
-        hipGraphExecDestroy(g_cache.front().exec);
+        destroy_entry(g_cache.front());
         g_cache.erase(g_cache.begin());
     }
-    g_cache.push_back({dev, *desc, exec});
+    hipEvent_t launched = nullptr;
+    if (hipEventCreateWithFlags(&launched, hipEventDisableTiming) != hipSuccess) launched = nullptr;
+    g_cache.push_back({dev, *desc, exec, launched});
     e = hipGraphLaunch(exec, s);
     if (e != hipSuccess) return bfail(LBM_ELAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
+    if (launched) hipEventRecord(launched, s);
     return LBM_OK;
 }
 
@@ -1106,7 +1119,7 @@ lbm_status lbm_batch_release(const lbm_batch_desc *desc) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t k = 0; k < g_cache.size();) {
         if (g_cache[k].dev == dev && same_desc(g_cache[k].d, *desc)) {
-            hipGraphExecDestroy(g_cache[k].exec);
+            destroy_entry(g_cache[k]);
             g_cache.erase(g_cache.begin() + (ptrdiff_t)k);
         } else {
             ++k;
