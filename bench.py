@@ -31,9 +31,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 # (profiles/k_step_12_d2q49_1024x1024_fp32.md), per tile shape; valid only for
 # the sources they were taken on (sha256 of the files below).
 TRAFFIC = {"nodes": 1024 * 1024, "inplace": True,
-           "bytes": {(16, 16): 522_077_399, (32, 8): 498_591_562, (32, 16): 476_071_477, (64, 2): 491_743_786, (64, 4): 490_428_396, (64, 8): 475_393_660, (128, 2): 490_100_131, (256, 1): 488_426_496},
-           "sha256": "97c76ffa246e60889cfc500938e320a924fe0746d7ff286764ed118950a6605b"}
-TRAFFIC_SOURCES = ('paper_1606_06107_amd/csrc/step_impl.hpp', 'paper_1606_06107_amd/csrc/lbm_device.hpp', 'paper_1606_06107_amd/csrc/launch.hpp', 'paper_1606_06107_amd/csrc/step_12_f32_inplace.hip', 'paper_1606_06107_amd/_build.py')
+           "bytes": {(16, 16): 522_077_399, (32, 8): 498_591_562, (32, 16): 476_071_477,
+                     (64, 2): 491_743_786, (64, 4): 490_428_396, (64, 8): 475_393_660,
+                     (128, 2): 490_100_131, (256, 1): 488_426_496},
+           "sha256":
+               "97c76ffa246e60889cfc500938e320a924fe0746d7ff286764ed118950a6605b"}
+TRAFFIC_SOURCES = ("paper_1606_06107_amd/csrc/step_impl.hpp", "paper_1606_06107_amd/csrc/lbm_device.hpp",
+                   "paper_1606_06107_amd/csrc/launch.hpp", "paper_1606_06107_amd/csrc/step_12_f32_inplace.hip",
+                   "paper_1606_06107_amd/_build.py")
 
 
 def kernel_sha():
