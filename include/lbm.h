@@ -333,7 +333,9 @@ lbm_status lbm_batch_init(const lbm_batch_desc *desc, const double *rho, const d
  * find the queue empty, and all of them once the long tubes are done, take
  * the tubes that fit on chip, which run their whole time loop there,
  * longest work first.  The result is left in f[0], g[0]; status[i] is
- * written by the end of the launch. */
+ * written by the end of the launch.  A tube with nsteps[i] = 0 is not read
+ * or written (status 0, 3 if empty; steps 0), so a call that advances a few
+ * tubes of a large batch costs only their work. */
 lbm_status lbm_batch_step(const lbm_batch_desc *desc, void *hip_stream);
 
 /* For callers that cannot allocate device memory or instantiate graphs

@@ -152,6 +152,15 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
         }
         return;
     }
+    // Tubes with no steps to run are finished here, as the queues would
+    // finish them: populations left in f[0] / g[0], no step taken, status 0
+    // (3 for an empty tube).  A call that advances a few tubes of a large
+    // batch then costs only those tubes' work.
+    for (int i = threadIdx.x; i < n; i += 1024)
+        if (a.nsteps[i] <= 0) {
+            a.status[i] = a.offsets[i + 1] > a.offsets[i] ? 0 : 3;
+            if (a.steps_done) a.steps_done[i] = 0;
+        }
     int P2 = 1;
     while (P2 < n) P2 <<= 1;
     __syncthreads();
@@ -160,8 +169,8 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
         unsigned long long k = 0;
         if (i < n) {
             const long long L = a.offsets[i + 1] - a.offsets[i];
-            if (L <= a.chunk) {
-                long long w = L * (a.nsteps[i] > 0 ? a.nsteps[i] : 0);
+            if (L <= a.chunk && a.nsteps[i] > 0) {
+                long long w = L * a.nsteps[i];
                 if (w > (1LL << 39) - 1) w = (1LL << 39) - 1;
                 k = ((unsigned long long)w << 24) | (unsigned long long)((1 << 24) - 1 - i);
                 atomicAdd(&s_cnt[0], 1);
@@ -179,8 +188,8 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a) {
         unsigned long long k = 0;
         if (i < n) {
             const long long L = a.offsets[i + 1] - a.offsets[i];
-            if (L > a.chunk) {
-                long long st = a.nsteps[i] > 0 ? a.nsteps[i] : 0;
+            if (L > a.chunk && a.nsteps[i] > 0) {
+                long long st = a.nsteps[i];
                 if (st > (1LL << 39) - 2) st = (1LL << 39) - 2;
                 k = ((unsigned long long)(st + 1) << 24) | (unsigned long long)((1 << 24) - 1 - i);
                 atomicAdd(&s_cnt[1], 1);

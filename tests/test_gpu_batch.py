@@ -221,6 +221,43 @@ def test_batch_substeps_equal_per_step_path_and_noalloc(torch_cuda):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("dtype,chunk,superstep", [("float64", 256, 8), ("float32", 0, 0)])
+def test_zero_step_tubes_are_left_alone(torch_cuda, dtype, chunk, superstep):
+    """Tubes with nsteps = 0 among stepped ones, on chip and chunked: their
+    populations bitwise unchanged, status 0 and 0 steps; the stepped tubes
+    against the oracle, and bitwise equal to a call that steps every tube."""
+    import torch
+    from paper_1606_06107_amd import Batch
+    announce(f"zero-step tubes {dtype} chunk={chunk}")
+    n_rot, tau, steps, rho, u, T, fields = _mild_batch(11)
+    zero = np.arange(len(LENGTHS)) % 3 == 1  # tubes 17, 255, 700, 2000 nodes
+    part = np.where(zero, 0, steps)
+    dt = getattr(torch_cuda, dtype)
+    b = Batch(LENGTHS, n_rot, tau, part, dtype=dt, chunk=chunk, superstep=superstep).init(rho, u, T)
+    full = Batch(LENGTHS, n_rot, tau, steps, dtype=dt, chunk=chunk, superstep=superstep).init(rho, u, T)
+    f_init, g_init = b.f[0].clone(), b.g[0].clone()
+    b.step()
+    full.step()
+    torch.cuda.synchronize()
+    st, done = b.status.cpu().numpy(), b.steps_done.cpu().numpy()
+    assert (st == 0).all()
+    assert (done == part).all()
+    off = b.offsets_h
+    for i in range(len(LENGTHS)):
+        sl = slice(int(off[i]), int(off[i + 1]))
+        if zero[i]:
+            assert torch.equal(b.f[0][:, sl], f_init[:, sl]) and torch.equal(b.g[0][:, sl], g_init[:, sl]), i
+        else:
+            assert torch.equal(b.f[0][:, sl], full.f[0][:, sl]) and torch.equal(b.g[0][:, sl], full.g[0][:, sl]), i
+    R, U, Tt = (b.split(m) for m in b.moments())
+    for i in np.flatnonzero(~zero):
+        ro, uo, To = _oracle_tube(fields[i], n_rot[i], tau[i], int(steps[i]))
+        tol = 1e-12 if dtype == "float64" else 1e-5
+        scale = (np.abs(ro).max(), max(np.abs(uo).max(), 1.0), np.abs(To).max()) if dtype == "float64" else (1, 1, 1)
+        for a_, b_, sc in ((R[i], ro, scale[0]), (U[i], uo[0], scale[1]), (Tt[i], To, scale[2])):
+            assert np.abs(a_ - b_).max() <= tol * sc, i
+
+
 def test_degenerate_calls(torch_cuda):
     """Zero steps change nothing (Sim.step(0); a batch whose tubes all have
     0 steps: status 0, 0 steps done, populations bitwise unchanged), and the
