@@ -559,8 +559,8 @@ def extra_surrogate(train_candidates=262144, test_candidates=4096, test_tubes=25
         gamma = torch.as_tensor(te.gamma, device="cuda")
         plain = Batch(te.lengths, te.n_rot, te.tau, np.full(te.num, 16 * calls), dtype=torch.float32)
         plain.init(te.rho, te.u[0], te.T)
-        # the fallback runs the few rejected tubes' remaining steps: latency-bound,
-        # so one node per thread in 1024-node chunks
+        # the fallback runs the few rejected tubes' remaining steps, latency-bound:
+        # one node per thread in 1024-node chunks, or the rollout's shape for few tubes
         fb = Batch(te.lengths, te.n_rot, te.tau, np.zeros(te.num, dtype=np.int64), dtype=torch.float32,
                    chunk=1024)
         return te, x0, gamma, plain, fb

@@ -84,18 +84,20 @@ class Batch:
             self.nsteps.copy_(torch.as_tensor(np.asarray(nsteps, dtype=np.int64)))
         cur.wait_stream(self.stream)
 
-    def step(self, stream=None, chunk=None):
+    def step(self, stream=None, chunk=None, superstep=None):
         """Advance every tube i by nsteps[i] steps (one persistent launch), on
-        the batch's stream or on `stream`; `chunk` overrides the batch's chunk
-        size for this call (0: the library's default shape)."""
+        the batch's stream or on `stream`; `chunk` and `superstep` override the
+        batch's launch shape for this call (0: the library's default)."""
         s = self._s() if stream is None else ctypes.c_void_p(stream.cuda_stream)
-        keep = self.desc.chunk
+        keep = self.desc.chunk, self.desc.superstep
         if chunk is not None:
             self.desc.chunk = int(chunk)
+        if superstep is not None:
+            self.desc.superstep = int(superstep)
         try:
             L.check(self.lib.lbm_batch_step(ctypes.byref(self.desc), s))
         finally:
-            self.desc.chunk = keep
+            self.desc.chunk, self.desc.superstep = keep
         return self
 
     def step_noalloc(self):

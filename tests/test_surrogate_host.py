@@ -32,3 +32,18 @@ def test_envelope_quantile_ignores_an_extreme_pair():
     env = SG.mach_envelope(x, x, 0.99)
     assert 1.3 < env < 1.6 and not math.isclose(env, 20.0)
     assert SG.mach_envelope(x, x, 1.0) == pytest.approx(20.0)
+
+
+@pytest.mark.parametrize("n,length,hw,want", [(1, 4096, 3, (256, 32)), (7, 4096, 3, (256, 24)),
+                                              (9, 4096, 3, (512, 60)), (34, 4096, 3, (768, 32)),
+                                              (129, 4096, 3, (0, 0)), (2, 512, 3, (256, 32)),
+                                              (1, 4096, 8, (768, 32))])
+def test_latency_shape_picks_the_first_shape_that_fits_one_round(n, length, hw, want):
+    """Chunks per pass = n * ceil(length / (chunk - 2 hw S)) against 1.1 x 256
+    compute units; a shape whose halos leave under 64 inner nodes is skipped;
+    none fits -> the library's default (0, 0)."""
+    assert SG.latency_shape(n, length, 256, hw=hw) == want
+    c, S = want
+    if c:
+        assert c - 2 * hw * S >= 64
+        assert n * -(-length // (c - 2 * hw * S)) <= 1.1 * 256
