@@ -508,6 +508,10 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, n32 = l & 31, hl = l >> 5;
     const int b = blockIdx.x / a.ntile, tile = blockIdx.x % a.ntile;
     if (a.active && !a.active[b]) return;  // workgroup-uniform
+    // First MLP biases of every block, read from LDS when each hidden tile's
+    // accumulators start (a global load there would stall the tile's MFMAs).
+    __shared__ __attribute__((aligned(16))) float B1s[NB * HID];
+    for (int e = threadIdx.x; e < NB * HID; e += 64 * FNW) B1s[e] = a.P[P_BLK + (e / HID) * BLK + B_B1 + e % HID];
     const int t0 = tile * FOUTR - FHALO;  // token of row 0
     const int r0 = 32 * w;
     const size_t BL = (size_t)a.B * a.L;
@@ -550,19 +554,33 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
         }
     }
 
+    // Weight fragments of the next hidden tile: those of block 0's first
+    // tile are issued here, every later tile's as soon as the products of
+    // the one before have read the registers (for a block's first tile, at
+    // the end of the previous block), so their latency overlaps other work.
+    bf16x8 w1[4], w2[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) w1[s] = ld_frag(a.Q + Q_BLK + Q_W1F + s * 512 + 8 * l);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) w2[f] = ld_frag(a.Q + Q_BLK + Q_W2F + f * 512 + 8 * l);
     for (int k = 0; k < NB; ++k) {
         const float *blk = a.P + P_BLK + k * BLK;
         const __bf16 *qb = a.Q + Q_BLK + k * QBLK;
+        // the block's convolution taps and second bias, loaded before the
+        // barrier so that it hides their latency
+        const int c = l;
+        float kc[TAPS];
+#pragma unroll
+        for (int q = 0; q < TAPS; ++q) kc[q] = blk[B_KC + c * TAPS + q];
+        const float bc = blk[B_BC + c];
+        float b2[2];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) b2[ot] = blk[B_B2 + 32 * ot + n32];
         __syncthreads();  // H of every row and its edge copies written
         const int par = k & 1;
         // Depthwise convolution: lane = channel, the wave's 32 rows.
         float hc[32];
         {
-            const int c = l;
-            float kc[TAPS];
-#pragma unroll
-            for (int q = 0; q < TAPS; ++q) kc[q] = blk[B_KC + c * TAPS + q];
-            const float bc = blk[B_BC + c];
             const float kc2 = kc[2] + 1.0f;  // the residual folded into the centre tap
             float win[36];
             // rows r0-2, r0-1 and r0+32, r0+33 from the neighbours' edge
@@ -594,23 +612,27 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
         for (int s = 0; s < 4; ++s) hb[s] = frag_from_f32(&Hf[(r0 + n32) * HS + 16 * s + 8 * hl]);
         f32x16 acc2[2];
 #pragma unroll
-        for (int ot = 0; ot < 2; ++ot) {
-            const float b2 = blk[B_B2 + 32 * ot + n32];
-            for (int i = 0; i < 16; ++i) acc2[ot][i] = b2;
-        }
+        for (int ot = 0; ot < 2; ++ot)
+            for (int i = 0; i < 16; ++i) acc2[ot][i] = b2[ot];
 #pragma unroll
         for (int h = 0; h < 4; ++h) {  // 32-wide hidden tiles
-            // The tile's eight weight fragments, issued together.
-            bf16x8 w1[4], w2[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) w1[s] = ld_frag(qb + Q_W1F + (4 * h + s) * 512 + 8 * l);
-#pragma unroll
-            for (int f = 0; f < 4; ++f) w2[f] = ld_frag(qb + Q_W2F + (4 * h + f) * 512 + 8 * l);
             f32x16 acc1;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc1[i] = blk[B_B1 + 32 * h + 8 * (i >> 2) + 4 * hl + (i & 3)];
+            for (int q = 0; q < 4; ++q) {
+                const float4 bv = *reinterpret_cast<const float4 *>(&B1s[k * HID + 32 * h + 8 * q + 4 * hl]);
+                acc1[4 * q] = bv.x;
+                acc1[4 * q + 1] = bv.y;
+                acc1[4 * q + 2] = bv.z;
+                acc1[4 * q + 3] = bv.w;
+            }
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[s], hb[s], acc1, 0, 0, 0);
+            // next tile: (k, h + 1), or block k + 1's first
+            const __bf16 *qn = h < 3 ? qb + (4 * (h + 1)) * 512 : qb + QBLK;
+            if (h < 3 || k + 1 < NB) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) w1[s] = ld_frag(qn + Q_W1F + s * 512 + 8 * l);
+            }
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {  // 16-wide hidden chunk 2 h + cc
                 bf16x8 af;
@@ -619,6 +641,10 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
 #pragma unroll
                 for (int ot = 0; ot < 2; ++ot)
                     acc2[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, w2[2 * cc + ot], acc2[ot], 0, 0, 0);
+            }
+            if (h < 3 || k + 1 < NB) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) w2[f] = ld_frag(qn + Q_W2F + f * 512 + 8 * l);
             }
         }
         // H' = Hc + (b2 + A1 W2^T) on the wave's rows (zero outside the tube).
