@@ -258,6 +258,35 @@ def test_zero_step_tubes_are_left_alone(torch_cuda, dtype, chunk, superstep):
             assert np.abs(a_ - b_).max() <= tol * sc, i
 
 
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_launch_shapes_give_the_same_bits(torch_cuda, dtype):
+    """The tubes of one batch advanced in the library's default shape and in
+    each latency shape of the surrogate's fallback (small chunks, long
+    passes; per-call chunk and superstep overrides): the same status, steps
+    and populations, bitwise -- halos are recomputed with the same per-node
+    arithmetic, and only nodes a full halo away from a chunk's cut are kept."""
+    import torch
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd.surrogate import LATENCY_SHAPES
+    announce(f"launch shapes, same bits ({dtype})")
+    n_rot, tau, steps, rho, u, T, _ = _mild_batch(12)
+    dt = getattr(torch_cuda, dtype)
+    b = Batch(LENGTHS, n_rot, tau, steps, dtype=dt)
+    ref = None
+    for shape in [(0, 0)] + list(LATENCY_SHAPES):
+        b.init(rho, u, T)
+        b.step(chunk=shape[0], superstep=shape[1])
+        torch.cuda.synchronize()
+        got = (b.status.cpu().numpy().copy(), b.steps_done.cpu().numpy().copy(),
+               b.f[0].cpu().numpy().copy(), b.g[0].cpu().numpy().copy())
+        assert (got[0] == 0).all() and np.array_equal(got[1], steps), shape
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[2], ref[2]) and np.array_equal(got[3], ref[3]), shape
+    b.release()
+
+
 def test_degenerate_calls(torch_cuda):
     """Zero steps change nothing (Sim.step(0); a batch whose tubes all have
     0 steps: status 0, 0 steps done, populations bitwise unchanged), and the
