@@ -66,12 +66,12 @@ def _time_calls(fn, reps, stream):
 def tune_sim(sim, steps=20, reps=5, finalists=3, force=False):
     """Pick the fastest tile of the per-step kernel for this Sim.
 
-    Round 1 times every compiled tile (median of `reps` calls of
-    step(steps)); round 2 times the `finalists` fastest again, interleaved
-    call by call so that drift of the clock or the memory affects them
-    alike, and picks the smallest median.  Advances the Sim.  Returns
-    (tile, table) with table = {"round1": {tile: ms per step},
-    "round2": {...}}."""
+    A first pass times every compiled tile (median of `reps` calls of
+    step(steps)); a second pass times the `finalists` fastest again,
+    interleaved call by call so that drift of the clock or the memory
+    affects them alike, and picks the smallest median.  Advances the Sim.
+    Returns (tile, table) with table = {"all": {tile: ms per step},
+    "finalists": {...}}."""
     _load()
     key = (f"step|D{sim.D}|lat{sim.lattice}|{sim.dtype}|{'x'.join(map(str, sim.shape))}|ip{sim._inplace}"
            f"|blk{sim._blocked}|{_arch()}")
@@ -108,7 +108,7 @@ def tune_sim(sim, steps=20, reps=5, finalists=3, force=False):
     best = min(r2, key=r2.get)
     bt = tuple(int(v) for v in best.split("x"))
     sim.set_tile(*bt)
-    table = {"round1": {k: round(v, 5) for k, v in r1.items()}, "round2": {k: round(v, 5) for k, v in r2.items()}}
+    table = {"all": {k: round(v, 5) for k, v in r1.items()}, "finalists": {k: round(v, 5) for k, v in r2.items()}}
     _mem[key] = {"best": list(bt), "table": table}
     _store()
     return bt, table
