@@ -219,16 +219,22 @@ def test_check_accepts_the_plain_scheme(torch_cuda):
     assert list(sur.check(xd, z, gd).cpu().numpy()) == [0, 1, 1]
 
 
-def test_rejecting_everything_reproduces_plain_lbm_bitwise(torch_cuda):
+@pytest.mark.parametrize("B,L", [(3, 512), (64, 4096)])
+def test_rejecting_everything_reproduces_plain_lbm_bitwise(torch_cuda, B, L):
     """With a check that rejects every step the rollout is the plain scheme:
     lifted once from the initial fields, then continued from its own
-    populations, bitwise equal to one uninterrupted batch run."""
-    announce("fallback == plain LBM")
+    populations, bitwise equal to one uninterrupted batch run.  The fallback
+    launch runs in a shape for few tubes (3 x 512 nodes) or, with too many
+    chunks for one round of the compute units (64 x 4096), in the library's
+    default shape."""
+    announce(f"fallback == plain LBM, B={B} L={L}")
     import torch
     import workloads
     from paper_1606_06107_amd import Batch
-    from paper_1606_06107_amd.surrogate import fields_of, rollout
-    B, L, calls = 3, 512, 4
+    from paper_1606_06107_amd.surrogate import fields_of, latency_shape, rollout
+    calls = 4
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert (latency_shape(B, L, cus) == (0, 0)) == (B == 64)
     bt = workloads.batched_tubes(B, seed=3, fixed_length=L, pr_range=(1.5, 3.0), dr_range=(1.0, 2.0))
     sur = _gpu(torch, S.init_params(0), B, L)
     plain = Batch(bt.lengths, bt.n_rot, bt.tau, np.full(B, 16 * calls), dtype=torch.float32)
