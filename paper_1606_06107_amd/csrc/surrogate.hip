@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(64 * FNW, 3) k_fwd_fused(FwdArgs a) {
         const float *blk = a.P + P_BLK + k * BLK;
         const __bf16 *qb = a.Q + Q_BLK + k * QBLK;
         // the block's convolution taps and second bias, loaded before the
-        // barrier so that it hides their latency
+        // barrier so that the wait there hides their latency
         const int c = l;
         float kc[TAPS];
 #pragma unroll
