@@ -759,6 +759,48 @@ def extra_placement(holds=8, hold_mb=192, steps=40):
             "rows": rows}
 
 
+def extra_fallback_shapes(demoted=(1, 7, 34, 129), steps=240, reps=6):
+    """The surrogate's fallback launch: `steps` plain steps for the first k
+    of 256 stable 4096-node tubes (the others have 0 steps), FP32, in the
+    fallback batch's own shape (1024-node chunks) and in each shape of
+    surrogate.LATENCY_SHAPES; per k the median time of `reps` calls and the
+    shape surrogate.latency_shape picks."""
+    import numpy as np
+    import torch
+
+    from paper_1606_06107_amd import Batch
+    from paper_1606_06107_amd import surrogate as SG
+    te = SG.stable_tubes(8192, seed=7)
+    te = te.subset(np.arange(min(256, te.num)))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rows = []
+    for k in demoted:
+        ns = np.zeros(te.num, dtype=np.int64)
+        ns[:k] = steps
+        b = Batch(te.lengths, te.n_rot, te.tau, ns, dtype=torch.float32, chunk=1024)
+        ms = {}
+        for c, S in [(0, 0)] + list(SG.LATENCY_SHAPES):
+            ts = []
+            for r in range(reps + 2):
+                b.init(te.rho, te.u[0], te.T)
+                a, e = _events(b.stream)
+                a.record(b.stream)
+                b.step(chunk=c, superstep=S) if c else b.step()
+                e.record(b.stream)
+                e.synchronize()
+                if r >= 2:
+                    ts.append(a.elapsed_time(e))
+            if not (b.status.cpu().numpy()[:k] == 0).all():
+                raise RuntimeError("a fallback tube failed")
+            ms[f"{c}x{S}" if c else "1024x24"] = round(float(np.median(ts)), 3)
+        b.release()
+        pick = SG.latency_shape(k, 4096, cus)
+        rows.append({"demoted_tubes": k, "ms_by_chunk_x_superstep": ms,
+                     "picked": f"{pick[0]}x{pick[1]}" if pick[0] else "1024x24"})
+    return {"workload": f"{steps} steps of k of {te.num} stable 4096-node tubes (the rest 0 steps), FP32 batch kernel",
+            "rows": rows}
+
+
 def pattern_probe(nx, ny, inplace, launches=40, blocked=False):
     """The step's memory pattern with no arithmetic (lbm_pattern_probe) on an
     nx x ny grid: ping-pong (alternating buffers) or in place (even and odd
@@ -844,7 +886,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", type=str,
                     default="hbm,tube_1d,turbulence_3d,d2q37,fd,transport,batched_tubes,surrogate",
-                    help="comma-separated subset of the extra workloads to run")
+                    help="comma-separated subset of the extra workloads to run (opt-in, not in the "
+                         "default: turbulence_3d_full, placement, fallback_shapes)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--sur-train-steps", type=int, default=120000,
                     help="Adam steps of the surrogate extra's training")
@@ -967,6 +1010,7 @@ def main():
         wanted = set(args.extras.split(","))
         for name, fn in (("hbm", extra_hbm), ("tube_1d", extra_tube_1d), ("turbulence_3d", extra_3d),
                          ("turbulence_3d_full", extra_3d_full), ("placement", extra_placement),
+                         ("fallback_shapes", extra_fallback_shapes),
                          ("d2q37", extra_d2q37), ("fd", extra_fd),
                          ("transport", extra_transport), ("batched_tubes", extra_batch),
                          ("surrogate", lambda: extra_surrogate(train_steps=args.sur_train_steps,
