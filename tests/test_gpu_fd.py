@@ -27,11 +27,13 @@ def _check(g, o, dtype):
 
 
 @pytest.mark.parametrize("shape,bc", [((150,), ["open"]), ((97,), ["periodic"]),
-                                      ((40, 24), ["periodic", "periodic"]), ((70, 19), ["open", "periodic"])])
+                                      ((40, 24), ["periodic", "periodic"]), ((70, 19), ["open", "periodic"]),
+                                      ((130, 9), ["periodic", "open"]), ((71, 6), ["periodic", "periodic"])])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_fd_vs_oracle(torch_cuda, shape, bc, dtype):
     """12 steps at Courant factor 0.15 from smooth fields plus a
-    non-equilibrium perturbation; ragged tiles (97, 150, 70x19)."""
+    non-equilibrium perturbation; ragged tiles (97, 150, 70x19, 130x9 with a
+    ragged second tile and an open y axis, 71x6)."""
     announce(f"FD {dtype} {shape} {bc}")
     fields = smooth_fields(shape, 4)
     dt = getattr(torch_cuda, dtype)
